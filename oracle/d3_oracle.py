@@ -1,0 +1,329 @@
+"""Plain FP64 NumPy oracle for D3 with Becke-Johnson damping.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): nothing in the
+product path may import this module.
+
+What it computes, and where each step comes from (Ying & Fan, "Combining
+the D3 dispersion correction with the neuroevolution machine-learned
+potential", Sec. II A):
+
+* entries: every ordered pair (i, j, T) of an atom i and an image j + T of
+  atom j (T a lattice translation, zero on open axes) with (j, T) != (i, 0)
+  and |r_j + T - r_i| below the cutoff.  Found by brute force over all j
+  and all translations that can reach the cutoff.  Cutoffs are hard: an
+  entry counts iff r^2 < R^2.
+* coordination number, Eq. 4: n_i = sum over entries with r < R_cn of
+  1 / (1 + exp(-16 ((Rcov_i + Rcov_j) / r - 1))).
+* C6, Eq. 3: the Gaussian-weighted (exponent -4) average of the reference
+  C6 values over all reference-CN pairs (a, b), evaluated per entry exactly
+  as printed.  All exponents of one entry are shifted by their maximum
+  first; the shift cancels between numerator and denominator and keeps
+  both sums representable.
+* C8 = C6 R0^2 and R0 the geometric mean of the per-species parameters
+  (text after Eq. 2).  The per-species parameter is sqrt(3) * r2r4, so
+  R0^2 = 3 r2r4_i r2r4_j (bohr^2), the usual BJ convention.
+* site energy, Eq. 2: U_i = -1/2 sum_j [s6 C6/(r^6 + Rd^6) + s8 C8/(r^8 + Rd^8)]
+  with Rd = a1 R0 + a2, over entries with r < R_pot; total energy Eq. 1.
+* forces: the exact negative gradient of the total energy.  Eqs. 5-6
+  state the many-body force through dU_i/dr_ij; because C6 depends on the
+  coordination numbers (the "two-body" term is really many-body, text
+  after Eq. 4), the gradient has a direct part at fixed C6 and a chain
+  part through dE/dn_k.
+* virial, Eq. 7 summed over atoms: W = -dE/d(strain), which for a finite
+  cluster equals sum_i r_i (x) F_i (eV).
+
+Units: Angstrom and eV.  The table arrives in Hartree*bohr^6 (C6) and bohr
+(r2r4) and is converted here with CODATA 2018 constants.
+
+Parity: pinned (closed forms, lattice sums, finite differences and
+invariances in the test suite; see the oracle pin tests).
+"""
+
+import numpy as np
+
+HARTREE_EV = 27.211386245988
+BOHR_ANG = 0.529177210903
+MAX_REF = 5
+
+
+class Params:
+    """Damping parameters and cutoffs (a2 and cutoffs in Angstrom)."""
+
+    def __init__(self, s6=1.0, a1=0.4289, s8=0.7875, a2=4.4407,
+                 r_pot=12.0, r_cn=6.0):
+        self.s6, self.a1, self.s8, self.a2 = s6, a1, s8, a2
+        self.r_pot, self.r_cn = r_pot, r_cn
+
+
+def convert_table(table):
+    """Per-element-pair constants in eV/Angstrom units."""
+    n_ref = np.asarray(table["n_ref"], dtype=np.int64)
+    cn_ref = np.asarray(table["cn_ref"], dtype=np.float64)
+    c6 = np.asarray(table["c6_ref"], dtype=np.float64) * HARTREE_EV * BOHR_ANG ** 6
+    r2r4 = np.asarray(table["r2r4"], dtype=np.float64)
+    r0sq = 3.0 * np.outer(r2r4, r2r4) * BOHR_ANG ** 2
+    return {"n_ref": n_ref, "cn_ref": cn_ref, "c6": c6,
+            "rcov": np.asarray(table["rcov"], dtype=np.float64), "r0sq": r0sq}
+
+
+def translations(cell, pbc, rmax, pos=None):
+    """All lattice translations n0 a + n1 b + n2 c that can bring an image of
+    one atom within rmax of another: on a periodic axis k, |n_k| <=
+    ceil(rmax/h_k + spread_k), where h_k is the distance between lattice
+    planes k and spread_k the extent of the atoms' fractional coordinate k
+    (below 1 for wrapped atoms); zero on open axes."""
+    cell = np.asarray(cell, dtype=np.float64)
+    vol = abs(np.linalg.det(cell))
+    if pos is not None and len(pos):
+        s = np.asarray(pos, dtype=np.float64) @ np.linalg.inv(cell)
+        spread = s.max(axis=0) - s.min(axis=0)
+    else:
+        spread = np.ones(3)
+    reach = []
+    for k in range(3):
+        if not pbc[k]:
+            reach.append(0)
+            continue
+        cr = np.cross(cell[(k + 1) % 3], cell[(k + 2) % 3])
+        h = vol / np.linalg.norm(cr)
+        reach.append(int(np.ceil(rmax / h + spread[k])))
+    rng = [np.arange(-m, m + 1) for m in reach]
+    n = np.stack(np.meshgrid(*rng, indexing="ij"), -1).reshape(-1, 3)
+    return n, n.astype(np.float64) @ cell
+
+
+def entries(pos, cell, pbc, rcut, rows=None):
+    """Brute-force entry list.  Returns (i, j, d) with d = r_j + T - r_i for
+    every (i, j, T) with (j,T) != (i,0) and |d|^2 < rcut^2.  ``rows``
+    restricts i to a subset (others are still candidates for j)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    if cell is None:
+        cell = np.eye(3)
+        pbc = (0, 0, 0)
+    nvec, tvec = translations(cell, pbc, rcut, pos)
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    rc2 = rcut * rcut
+    out_i, out_j, out_d = [], [], []
+    chunk = max(1, 4_000_000 // max(1, n * len(tvec)))
+    for s in range(0, len(rows), chunk):
+        ii = rows[s:s + chunk]
+        for t, T in zip(nvec, tvec):
+            d = pos[None, :, :] + T[None, None, :] - pos[ii][:, None, :]
+            r2 = np.einsum("abk,abk->ab", d, d)
+            m = r2 < rc2
+            if not np.any(t):
+                m[np.arange(len(ii)), ii] = False
+            a, b = np.nonzero(m)
+            out_i.append(ii[a])
+            out_j.append(b)
+            out_d.append(d[a, b])
+    if not out_i:
+        return (np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros((0, 3)))
+    return (np.concatenate(out_i).astype(np.int64),
+            np.concatenate(out_j).astype(np.int64),
+            np.concatenate(out_d, axis=0))
+
+
+def counting(r, rs):
+    """Eq. 4 counting function and its r-derivative."""
+    e = np.exp(-16.0 * (rs / r - 1.0))
+    f = 1.0 / (1.0 + e)
+    df = -16.0 * rs * e / (r * r * (1.0 + e) ** 2)
+    return f, df
+
+
+def coordination(n_atoms, types, tab, i, j, d, r_cn):
+    """Eq. 4 summed over entries with r < R_cn."""
+    r2 = np.einsum("ek,ek->e", d, d)
+    m = r2 < r_cn * r_cn
+    r = np.sqrt(r2[m])
+    rs = tab["rcov"][types[i[m]]] + tab["rcov"][types[j[m]]]
+    f, _ = counting(r, rs)
+    return np.bincount(i[m], weights=f, minlength=n_atoms)
+
+
+def c6_eq3(zi, zj, ni, nj, tab):
+    """Eq. 3 per entry, with its derivatives wrt n_i and n_j.
+
+    Exponent of pair (a,b): x_ab = -4[(n_i - ref_ia)^2 + (n_j - ref_jb)^2];
+    C6 = sum_ab C_ab e^{x_ab} / sum_ab e^{x_ab} (after subtracting max x_ab).
+    """
+    zi = np.asarray(zi)
+    zj = np.asarray(zj)
+    ni = np.asarray(ni, dtype=np.float64)
+    nj = np.asarray(nj, dtype=np.float64)
+    ki = tab["n_ref"][zi]
+    kj = tab["n_ref"][zj]
+    ref_i = tab["cn_ref"][zi]                       # (E,5)
+    ref_j = tab["cn_ref"][zj]
+    valid = (np.arange(MAX_REF)[None, :, None] < ki[:, None, None]) & \
+            (np.arange(MAX_REF)[None, None, :] < kj[:, None, None])
+    di = ni[:, None] - ref_i                        # (E,5)
+    dj = nj[:, None] - ref_j
+    x = -4.0 * (di[:, :, None] ** 2 + dj[:, None, :] ** 2)
+    x = np.where(valid, x, -np.inf)
+    x = x - x.max(axis=(1, 2), keepdims=True)
+    L = np.exp(x)                                   # zero where invalid
+    C = tab["c6"][zi, zj]                           # (E,5,5)
+    Z = L.sum(axis=(1, 2))
+    S = (C * L).sum(axis=(1, 2))
+    c6 = S / Z
+    dxi = np.where(valid, -8.0 * di[:, :, None], 0.0)
+    dxj = np.where(valid, -8.0 * dj[:, None, :], 0.0)
+    dc6_dni = ((C * L * dxi).sum(axis=(1, 2)) - c6 * (L * dxi).sum(axis=(1, 2))) / Z
+    dc6_dnj = ((C * L * dxj).sum(axis=(1, 2)) - c6 * (L * dxj).sum(axis=(1, 2))) / Z
+    return c6, dc6_dni, dc6_dnj
+
+
+def pair_terms(r2, zi, zj, c6, tab, prm):
+    """Eq. 2 pair energy phi (both halves), d phi/dr divided by r, and
+    d phi / d C6, at fixed C6."""
+    r0sq = tab["r0sq"][zi, zj]
+    rd = prm.a1 * np.sqrt(r0sq) + prm.a2
+    r6 = r2 ** 3
+    r8 = r2 ** 4
+    rd6 = rd ** 6
+    rd8 = rd ** 8
+    t6 = 1.0 / (r6 + rd6)
+    t8 = 1.0 / (r8 + rd8)
+    c8 = c6 * r0sq
+    phi = -(prm.s6 * c6 * t6 + prm.s8 * c8 * t8)
+    # d/dr [-C/(r^k + Rd^k)] = C k r^(k-1) / (r^k + Rd^k)^2 ; divide by r
+    dphi_r = prm.s6 * c6 * 6.0 * r2 * r2 * t6 * t6 + \
+        prm.s8 * c8 * 8.0 * r6 * t8 * t8
+    dphi_dc6 = -(prm.s6 * t6 + prm.s8 * r0sq * t8)
+    return phi, dphi_r, dphi_dc6
+
+
+def d3(pos, types, cell, pbc, table, prm=None):
+    """Full FP64 evaluation.  Returns dict with energy, forces (N,3),
+    virial (3,3), atom_energy (N), cn (N), dE/dn (N)."""
+    prm = prm or Params()
+    tab = convert_table(table)
+    pos = np.asarray(pos, dtype=np.float64)
+    types = np.asarray(types, dtype=np.int64)
+    n = pos.shape[0]
+    i, j, d = entries(pos, cell, pbc, max(prm.r_pot, prm.r_cn))
+    return _evaluate(n, types, tab, prm, i, j, d)
+
+
+def _evaluate(n, types, tab, prm, i, j, d, cn=None):
+    r2 = np.einsum("ek,ek->e", d, d)
+    if cn is None:
+        cn = coordination(n, types, tab, i, j, d, prm.r_cn)
+    # dispersion entries
+    mp = r2 < prm.r_pot * prm.r_pot
+    ip, jp, dp, r2p = i[mp], j[mp], d[mp], r2[mp]
+    zi, zj = types[ip], types[jp]
+    c6, dci, _ = c6_eq3(zi, zj, cn[ip], cn[jp], tab)
+    phi, dphi_r, dphi_dc6 = pair_terms(r2p, zi, zj, c6, tab, prm)
+    atom_e = 0.5 * np.bincount(ip, weights=phi, minlength=n)
+    dedn = np.bincount(ip, weights=dphi_dc6 * dci, minlength=n)
+    forces = np.zeros((n, 3))
+    for k in range(3):
+        forces[:, k] += np.bincount(ip, weights=dphi_r * dp[:, k], minlength=n)
+    vir = -0.5 * np.einsum("e,ea,eb->ab", dphi_r, dp, dp)
+    # chain entries through the coordination numbers
+    mc = r2 < prm.r_cn * prm.r_cn
+    ic, jc, dc, r2c = i[mc], j[mc], d[mc], r2[mc]
+    rc = np.sqrt(r2c)
+    rs = tab["rcov"][types[ic]] + tab["rcov"][types[jc]]
+    _, df = counting(rc, rs)
+    coef = (dedn[ic] + dedn[jc]) * df / rc
+    for k in range(3):
+        forces[:, k] += np.bincount(ic, weights=coef * dc[:, k], minlength=n)
+    vir += -0.5 * np.einsum("e,ea,eb->ab", coef, dc, dc)
+    return {"energy": float(atom_e.sum()), "forces": forces, "virial": vir,
+            "atom_energy": atom_e, "cn": cn, "dedn": dedn}
+
+
+def energy_only(pos, types, cell, pbc, table, prm=None):
+    """Total energy alone (used by finite-difference pins)."""
+    prm = prm or Params()
+    tab = convert_table(table)
+    pos = np.asarray(pos, dtype=np.float64)
+    types = np.asarray(types, dtype=np.int64)
+    n = pos.shape[0]
+    i, j, d = entries(pos, cell, pbc, max(prm.r_pot, prm.r_cn))
+    r2 = np.einsum("ek,ek->e", d, d)
+    cn = coordination(n, types, tab, i, j, d, prm.r_cn)
+    mp = r2 < prm.r_pot * prm.r_pot
+    zi, zj = types[i[mp]], types[j[mp]]
+    c6, _, _ = c6_eq3(zi, zj, cn[i[mp]], cn[j[mp]], tab)
+    phi, _, _ = pair_terms(r2[mp], zi, zj, c6, tab, prm)
+    return 0.5 * phi.sum()
+
+
+def sampled(pos, types, cell, pbc, table, idx, prm=None):
+    """Forces, site energies, coordination numbers and dE/dn of the atoms
+    ``idx`` of a large cell, each computed from its own neighbourhood.
+
+    The force on k depends on n_j for j within R_pot of k and on dE/dn_j for
+    j within R_cn of k; dE/dn_j depends on n_l for l within R_pot of j, and
+    n_l on atoms within R_cn of l.  So every quantity needed for atom k is
+    fixed by the images within R_pot + 2 R_cn of k, and the full definition
+    restricted to that ball gives the exact result."""
+    prm = prm or Params()
+    tab = convert_table(table)
+    pos = np.asarray(pos, dtype=np.float64)
+    types = np.asarray(types, dtype=np.int64)
+    rbig = prm.r_pot + 2.0 * prm.r_cn + 1e-6
+    nvec, tvec = translations(cell, pbc, rbig, pos)
+    res = {"forces": [], "atom_energy": [], "cn": [], "dedn": []}
+    for k in np.asarray(idx):
+        loc_pos, loc_atom = [], []
+        for T in tvec:
+            d = pos + T - pos[k]
+            r2 = np.einsum("ak,ak->a", d, d)
+            m = np.nonzero(r2 < rbig * rbig)[0]
+            loc_pos.append(d[m])
+            loc_atom.append(m)
+        lp = np.concatenate(loc_pos)
+        la = np.concatenate(loc_atom)
+        lt = types[la]
+        dist = np.sqrt(np.einsum("ak,ak->a", lp, lp))
+        me = int(np.nonzero((la == k) & (dist == 0.0))[0][0])
+        nl = lp.shape[0]
+        # n for local images within R_pot + R_cn of k (all their CN
+        # neighbours lie inside the ball)
+        need_n = np.nonzero(dist < prm.r_pot + prm.r_cn + 1e-9)[0]
+        cn = np.full(nl, np.nan)
+        for a in need_n:
+            dd = lp - lp[a]
+            rr = np.einsum("ak,ak->a", dd, dd)
+            m = rr < prm.r_cn * prm.r_cn
+            m[a] = False
+            f, _ = counting(np.sqrt(rr[m]), tab["rcov"][lt[a]] + tab["rcov"][lt[m]])
+            cn[a] = f.sum()
+        # dE/dn for local images within R_cn of k
+        need_g = np.nonzero(dist < prm.r_cn + 1e-9)[0]
+        g = np.full(nl, np.nan)
+        for a in need_g:
+            dd = lp - lp[a]
+            rr = np.einsum("ak,ak->a", dd, dd)
+            m = rr < prm.r_pot * prm.r_pot
+            m[a] = False
+            zi = np.full(int(m.sum()), lt[a])
+            c6, dci, _ = c6_eq3(zi, lt[m], np.full(zi.size, cn[a]), cn[m], tab)
+            _, _, dphi_dc6 = pair_terms(rr[m], zi, lt[m], c6, tab, prm)
+            g[a] = (dphi_dc6 * dci).sum()
+        # force and site energy of k
+        dd = lp - lp[me]
+        rr = np.einsum("ak,ak->a", dd, dd)
+        m = rr < prm.r_pot * prm.r_pot
+        m[me] = False
+        zi = np.full(int(m.sum()), lt[me])
+        c6, _, _ = c6_eq3(zi, lt[m], np.full(zi.size, cn[me]), cn[m], tab)
+        phi, dphi_r, _ = pair_terms(rr[m], zi, lt[m], c6, tab, prm)
+        f = (dphi_r[:, None] * dd[m]).sum(0)
+        mc = rr < prm.r_cn * prm.r_cn
+        mc[me] = False
+        rc = np.sqrt(rr[mc])
+        _, df = counting(rc, tab["rcov"][lt[me]] + tab["rcov"][lt[mc]])
+        f += (((g[me] + g[mc]) * df / rc)[:, None] * dd[mc]).sum(0)
+        res["forces"].append(f)
+        res["atom_energy"].append(0.5 * phi.sum())
+        res["cn"].append(cn[me])
+        res["dedn"].append(g[me])
+    return {k: np.asarray(v) for k, v in res.items()}

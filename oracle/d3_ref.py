@@ -1,0 +1,84 @@
+"""ctypes wrapper of the plain C FP64 oracle (oracle/d3_ref.c).
+
+TEST INFRASTRUCTURE ONLY: see the package docstring.
+"""
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "d3_ref.c")
+_LIB = os.path.join(_HERE, "libd3ref.so")
+_lib = None
+
+
+def build(force=False):
+    """Compile the C oracle with gcc -O2 -fopenmp."""
+    if force or not os.path.exists(_LIB) or \
+            os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".%d.tmp" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        D = ctypes.c_double
+        I = ctypes.c_int
+        lib.d3ref_evaluate.restype = ctypes.c_long
+        lib.d3ref_evaluate.argtypes = [I, P, P, P, P, I, P, P, P, P, P,
+                                       D, D, D, D, D, D, I,
+                                       P, P, P, P, P, P]
+        lib.d3ref_threads.restype = I
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def threads():
+    return _load().d3ref_threads()
+
+
+def d3(pos, types, cell, pbc, table, s6=1.0, a1=0.4289, s8=0.7875, a2=4.4407,
+       r_pot=12.0, r_cn=6.0, n_threads=0):
+    """Full FP64 evaluation; returns the same dict layout as
+    d3_oracle.d3 plus the number of dispersion entries."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    types = np.ascontiguousarray(types, dtype=np.int32)
+    cellp = None if cell is None else np.ascontiguousarray(cell, dtype=np.float64)
+    pbcp = None if cell is None else np.ascontiguousarray(pbc, dtype=np.int32)
+    n_ref = np.ascontiguousarray(table["n_ref"], dtype=np.int32)
+    ne = n_ref.shape[0]
+    cn_ref = np.ascontiguousarray(table["cn_ref"], dtype=np.float64)
+    c6 = np.ascontiguousarray(table["c6_ref"], dtype=np.float64)
+    rcov = np.ascontiguousarray(table["rcov"], dtype=np.float64)
+    r2r4 = np.ascontiguousarray(table["r2r4"], dtype=np.float64)
+    energy = np.zeros(1)
+    forces = np.zeros((n, 3))
+    virial = np.zeros((3, 3))
+    ae = np.zeros(n)
+    cn = np.zeros(n)
+    g = np.zeros(n)
+    total = lib.d3ref_evaluate(
+        n, _ptr(pos), _ptr(types), _ptr(cellp), _ptr(pbcp), ne, _ptr(n_ref),
+        _ptr(cn_ref), _ptr(c6), _ptr(rcov), _ptr(r2r4), s6, a1, s8, a2,
+        r_pot, r_cn, int(n_threads), _ptr(energy), _ptr(forces),
+        _ptr(virial), _ptr(ae), _ptr(cn), _ptr(g))
+    if total < 0:
+        raise MemoryError("d3ref_evaluate failed")
+    return {"energy": float(energy[0]), "forces": forces, "virial": virial,
+            "atom_energy": ae, "cn": cn, "dedn": g, "n_entries": int(total)}

@@ -1,0 +1,484 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by
+mathematics, independent of the oracle's own code path.
+
+Each test names the part of the method it pins (Ying & Fan, Sec. II A,
+Eqs. 1-7) and what would break it.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import d3_oracle as O
+from oracle import d3_ref as R
+
+HARTREE_EV = 27.211386245988
+BOHR_ANG = 0.529177210903
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _table(**kw):
+    return synth.make_table(**kw)
+
+
+def _dimer(za, zb, r):
+    pos = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]])
+    return pos, np.array([za, zb], dtype=np.int32)
+
+
+def _free_energy(pos, types, tab, prm):
+    return O.energy_only(pos, types, None, (0, 0, 0), tab, prm)
+
+
+# --------------------------------------------------------------- Eq. 4 ----
+
+def test_counting_function_is_half_at_covalent_sum():
+    """Eq. 4: the counting function is exactly 1/2 at r = Rcov_i + Rcov_j,
+    so a dimer at that distance has n_1 = n_2 = 1/2 (catches a wrong sign,
+    a swapped ratio or a wrong radius sum)."""
+    tab = _table()
+    for za, zb in [(0, 1), (1, 1), (2, 4), (3, 0)]:
+        r = tab["rcov"][za] + tab["rcov"][zb]
+        pos, types = _dimer(za, zb, r)
+        res = O.d3(pos, types, None, (0, 0, 0), tab, O.Params(r_cn=6.0))
+        assert res["cn"] == pytest.approx([0.5, 0.5], abs=1e-15)
+
+
+def test_cn_dimer_closed_form_and_cutoff():
+    """Eq. 4 dimer closed form 1/(1+exp(-16(Rs/r-1))), and n = 0 once the
+    pair lies beyond R_cn (hard cutoff)."""
+    tab = _table()
+    for r in [0.9, 1.3, 2.2, 4.0, 5.99]:
+        pos, types = _dimer(1, 3, r)
+        rs = tab["rcov"][1] + tab["rcov"][3]
+        want = 1.0 / (1.0 + np.exp(-16.0 * (rs / r - 1.0)))
+        res = O.d3(pos, types, None, (0, 0, 0), tab, O.Params(r_cn=6.0))
+        assert res["cn"] == pytest.approx([want, want], rel=1e-14)
+    pos, types = _dimer(1, 3, 6.01)
+    res = O.d3(pos, types, None, (0, 0, 0), tab, O.Params(r_cn=6.0))
+    assert np.all(res["cn"] == 0.0)
+
+
+def test_cn_simple_cubic_shells():
+    """Eq. 4 summed over lattice images: in a simple-cubic crystal with
+    lattice constant a and R_cn between sqrt(3)a and 2a, n = 6 f(a) +
+    12 f(sqrt2 a) + 8 f(sqrt3 a) (coordination shells 6, 12, 8)."""
+    tab = _table()
+    a = 1.5
+    lat = synth.simple_lattice("sc", a, element=1)
+    rs = 2.0 * tab["rcov"][1]
+
+    def f(r):
+        return 1.0 / (1.0 + np.exp(-16.0 * (rs / r - 1.0)))
+
+    want = 6 * f(a) + 12 * f(np.sqrt(2) * a) + 8 * f(np.sqrt(3) * a)
+    res = O.d3(lat["pos"], lat["types"], lat["cell"], lat["pbc"], tab,
+               O.Params(r_cn=2.8, r_pot=2.8))
+    assert res["cn"][0] == pytest.approx(want, rel=1e-14)
+
+
+# --------------------------------------------------------------- Eq. 3 ----
+
+def test_c6_single_reference_is_the_reference():
+    """Eq. 3 with one reference point per element: C6 = C6ref for any CN
+    and dC6/dn = 0."""
+    tab = O.convert_table(_table(force_k=1))
+    zi = np.array([0, 1, 4, 2, 3])
+    zj = np.array([4, 1, 0, 3, 3])
+    ni = np.array([0.0, 1.3, 7.5, 30.0, 2.0])
+    nj = np.array([5.0, 0.1, 2.2, 0.0, 60.0])
+    c6, di, dj = O.c6_eq3(zi, zj, ni, nj, tab)
+    raw = _table(force_k=1)["c6_ref"][zi, zj, 0, 0] * HARTREE_EV * BOHR_ANG ** 6
+    assert c6 == pytest.approx(raw, rel=1e-14)
+    assert np.abs(di).max() <= 1e-13 * raw.max()
+    assert np.abs(dj).max() <= 1e-13 * raw.max()
+
+
+def test_c6_two_reference_logistic_closed_form():
+    """Eq. 3 with K_i = 2 and K_j = 1 reduces to a logistic blend:
+    C6 = C1 + (C2 - C1) s(8 (r2 - r1)(n_i - (r1 + r2)/2)), s the logistic
+    function, because the two Gaussian weights differ by
+    exp(-4 (r2 - r1)(2 n_i - r1 - r2)).  Its n_i-derivative follows."""
+    raw = _table()
+    e = int(np.nonzero(raw["n_ref"] == 2)[0][0])
+    f = int(np.nonzero(raw["n_ref"] == 1)[0][0])
+    tab = O.convert_table(raw)
+    r1, r2 = tab["cn_ref"][e, 0], tab["cn_ref"][e, 1]
+    c1, c2 = tab["c6"][e, f, 0, 0], tab["c6"][e, f, 1, 0]
+    ni = np.linspace(-1.0, 6.0, 57)
+    z = 8.0 * (r2 - r1) * (ni - 0.5 * (r1 + r2))
+    s = 1.0 / (1.0 + np.exp(-z))
+    want = c1 + (c2 - c1) * s
+    dwant = (c2 - c1) * s * (1.0 - s) * 8.0 * (r2 - r1)
+    c6, di, dj = O.c6_eq3(np.full(ni.size, e), np.full(ni.size, f), ni,
+                          np.full(ni.size, 2.5), tab)
+    assert c6 == pytest.approx(want, rel=1e-13)
+    assert di == pytest.approx(dwant, rel=1e-9, abs=1e-12 * abs(c2 - c1))
+    # K_j = 1: no dependence on n_j (zero up to rounding)
+    assert np.abs(dj).max() <= 1e-13 * max(c1, c2)
+
+
+def test_c6_limits_at_separated_references():
+    """Eq. 3 at a reference point far (>= 3 CN units) from every other
+    reference returns that reference's C6 to within exp(-36)."""
+    raw = _table(force_k=2)
+    raw["cn_ref"][:, 0] = 0.0
+    raw["cn_ref"][:, 1] = 3.5
+    tab = O.convert_table(raw)
+    for a, na in ((0, 0.0), (1, 3.5)):
+        for b, nb in ((0, 0.0), (1, 3.5)):
+            c6, _, _ = O.c6_eq3(np.array([1]), np.array([4]), np.array([na]),
+                                np.array([nb]), tab)
+            assert c6[0] == pytest.approx(tab["c6"][1, 4, a, b], rel=1e-15)
+
+
+def test_c6_symmetry_and_derivatives():
+    """C6_ef(n_i, n_j) = C6_fe(n_j, n_i) (the table is symmetric), and the
+    analytic CN derivatives agree with central differences of C6."""
+    tab = O.convert_table(_table())
+    rng = np.random.default_rng(5)
+    zi = rng.integers(0, 5, 200)
+    zj = rng.integers(0, 5, 200)
+    ni = rng.uniform(0, 5, 200)
+    nj = rng.uniform(0, 5, 200)
+    a, dai, daj = O.c6_eq3(zi, zj, ni, nj, tab)
+    b, dbi, dbj = O.c6_eq3(zj, zi, nj, ni, tab)
+    assert a == pytest.approx(b, rel=1e-13)
+    assert dai == pytest.approx(dbj, rel=1e-11, abs=1e-9)
+    h = 1e-6
+    p, _, _ = O.c6_eq3(zi, zj, ni + h, nj, tab)
+    m, _, _ = O.c6_eq3(zi, zj, ni - h, nj, tab)
+    assert dai == pytest.approx((p - m) / (2 * h), rel=1e-6, abs=1e-5)
+    p, _, _ = O.c6_eq3(zi, zj, ni, nj + h, tab)
+    m, _, _ = O.c6_eq3(zi, zj, ni, nj - h, tab)
+    assert daj == pytest.approx((p - m) / (2 * h), rel=1e-6, abs=1e-5)
+
+
+def test_c6_no_underflow_far_from_references():
+    """Eq. 3 stays finite (and equals the nearest reference blend) when the
+    CN is so far from every reference that every raw Gaussian underflows."""
+    tab = O.convert_table(_table())
+    c6, di, dj = O.c6_eq3(np.array([0]), np.array([4]), np.array([40.0]),
+                          np.array([35.0]), tab)
+    assert np.isfinite(c6).all() and np.isfinite(di).all()
+    k0 = tab["n_ref"][0] - 1
+    k4 = tab["n_ref"][4] - 1
+    # largest reference CN dominates; the tie breaks only if refs coincide
+    assert c6[0] == pytest.approx(tab["c6"][0, 4, k0, k4], rel=1e-6)
+
+
+# --------------------------------------------------------- Eqs. 1-2 -------
+
+def test_dimer_energy_closed_form():
+    """Eqs. 1-2 for a single-reference dimer: E(r) = -s6 C6/(r^6 + Rd^6)
+    - s8 C6 R0^2/(r^8 + Rd^8) with R0^2 = 3 r2r4_i r2r4_j bohr^2 and
+    Rd = a1 R0 + a2; the two site energies are equal halves."""
+    raw = _table(force_k=1)
+    prm = O.Params(r_pot=12.0, r_cn=6.0)
+    for za, zb in [(0, 4), (1, 1), (2, 3)]:
+        c6 = raw["c6_ref"][za, zb, 0, 0] * HARTREE_EV * BOHR_ANG ** 6
+        r0 = np.sqrt(3.0 * raw["r2r4"][za] * raw["r2r4"][zb]) * BOHR_ANG
+        rd = prm.a1 * r0 + prm.a2
+        for r in [1.0, 2.5, 4.4, 8.0, 11.9]:
+            pos, types = _dimer(za, zb, r)
+            res = O.d3(pos, types, None, (0, 0, 0), raw, prm)
+            want = -(prm.s6 * c6 / (r ** 6 + rd ** 6) +
+                     prm.s8 * c6 * r0 ** 2 / (r ** 8 + rd ** 8))
+            assert res["energy"] == pytest.approx(want, rel=1e-13)
+            assert res["atom_energy"] == pytest.approx([want / 2, want / 2],
+                                                       rel=1e-13)
+            dE = (prm.s6 * c6 * 6 * r ** 5 / (r ** 6 + rd ** 6) ** 2 +
+                  prm.s8 * c6 * r0 ** 2 * 8 * r ** 7 / (r ** 8 + rd ** 8) ** 2)
+            # atom 2 sits at +x: F_2 = -dE/dr, F_1 = +dE/dr
+            assert res["forces"][1, 0] == pytest.approx(-dE, rel=1e-12)
+            assert res["forces"][0, 0] == pytest.approx(dE, rel=1e-12)
+        pos, types = _dimer(za, zb, 12.0001)
+        assert O.d3(pos, types, None, (0, 0, 0), raw, prm)["energy"] == 0.0
+
+
+def test_damping_limits():
+    """Eq. 2 limits: s8 = 0 keeps only the C6 term; a1 = a2 = 0 gives the
+    undamped -C6/r^6 - C8/r^8; far away the C6 tail dominates."""
+    raw = _table(force_k=1)
+    c6 = raw["c6_ref"][1, 1, 0, 0] * HARTREE_EV * BOHR_ANG ** 6
+    r0sq = 3.0 * raw["r2r4"][1] ** 2 * BOHR_ANG ** 2
+    pos, types = _dimer(1, 1, 3.0)
+    e = O.d3(pos, types, None, (0, 0, 0), raw,
+             O.Params(a1=0.0, a2=0.0, s8=0.0))["energy"]
+    assert e == pytest.approx(-c6 / 3.0 ** 6, rel=1e-14)
+    e = O.d3(pos, types, None, (0, 0, 0), raw,
+             O.Params(a1=0.0, a2=0.0, s8=1.0))["energy"]
+    assert e == pytest.approx(-c6 / 3.0 ** 6 - c6 * r0sq / 3.0 ** 8, rel=1e-14)
+    pos, types = _dimer(1, 1, 400.0)
+    e = O.d3(pos, types, None, (0, 0, 0), raw, O.Params(r_pot=500.0))["energy"]
+    assert e == pytest.approx(-c6 / 400.0 ** 6, rel=1e-6)
+
+
+def _golden_lattice():
+    rows = []
+    with open(os.path.join(GOLDEN, "lattice_sums.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, a6, tol = line.split()
+                rows.append((k, float(a6), float(tol)))
+    return rows
+
+
+@pytest.mark.parametrize("kind,a6,tol", _golden_lattice())
+def test_lattice_sum_constants(kind, a6, tol):
+    """Eqs. 1-2 summed over periodic images reproduce the classic lattice
+    sums: with one reference (constant C6), s8 = 0 and no damping, the
+    energy per atom of a cubic crystal is -1/2 C6 A6 / d_nn^6 (A6 from the
+    golden file) once the cutoff tail, 2 pi rho/(3 R^3) per atom in the
+    continuum limit, is added back."""
+    raw = _table(force_k=1)
+    c6 = raw["c6_ref"][1, 1, 0, 0] * HARTREE_EV * BOHR_ANG ** 6
+    a = 4.0
+    lat = synth.simple_lattice(kind, a, element=1)
+    dnn = {"sc": a, "bcc": a * np.sqrt(3) / 2, "fcc": a / np.sqrt(2)}[kind]
+    rcut = 30.0 * a
+    nat = lat["pos"].shape[0]
+    rho = nat / a ** 3
+    res = R.d3(lat["pos"], lat["types"], lat["cell"], lat["pbc"], raw,
+               s6=1.0, a1=0.0, s8=0.0, a2=0.0, r_pot=rcut, r_cn=0.5)
+    tail = 0.5 * c6 * 4.0 * np.pi * rho / (3.0 * rcut ** 3)
+    e_atom = res["energy"] / nat - tail
+    want = -0.5 * c6 * a6 / dnn ** 6
+    assert e_atom == pytest.approx(want, rel=tol)
+
+
+# ----------------------------------------------------- Eqs. 5-7 -----------
+
+def _fd_forces(pos, types, cell, pbc, tab, prm, h=1e-5, atoms=None):
+    atoms = range(pos.shape[0]) if atoms is None else atoms
+    out = {}
+    for a in atoms:
+        f = np.zeros(3)
+        for k in range(3):
+            p = pos.copy()
+            p[a, k] += h
+            ep = O.energy_only(p, types, cell, pbc, tab, prm)
+            p[a, k] -= 2 * h
+            em = O.energy_only(p, types, cell, pbc, tab, prm)
+            f[k] = -(ep - em) / (2 * h)
+        out[a] = f
+    return out
+
+
+def _min_gap_to_cutoffs(pos, cell, pbc, prm):
+    i, j, d = O.entries(pos, cell, pbc, max(prm.r_pot, prm.r_cn) + 0.5)
+    r = np.linalg.norm(d, axis=1)
+    return min(np.abs(r - prm.r_pot).min(), np.abs(r - prm.r_cn).min())
+
+
+def test_forces_match_finite_differences_cluster():
+    """Forces are -grad E including the chain term through the CNs (the
+    many-body remark after Eq. 4): central differences on a cluster whose
+    diameter is below both cutoffs (no cutoff crossings)."""
+    tab = _table()
+    c = synth.cluster(24, 4.0, seed=11)
+    prm = O.Params(r_pot=12.0, r_cn=9.0)
+    res = O.d3(c["pos"], c["types"], None, (0, 0, 0), tab, prm)
+    fd = _fd_forces(c["pos"], c["types"], None, (0, 0, 0), tab, prm)
+    scale = np.abs(res["forces"]).max()
+    for a, f in fd.items():
+        assert f == pytest.approx(res["forces"][a], abs=1e-8 + 1e-7 * scale)
+
+
+def test_forces_match_finite_differences_periodic_triclinic():
+    """Same pin in a small triclinic periodic cell where several images of
+    one atom lie inside R_pot (self-image entries included); the geometry
+    keeps every entry more than 1e-3 A from either cutoff."""
+    tab = _table()
+    rng = np.random.default_rng(3)
+    cell = np.array([[7.0, 0.0, 0.0], [2.1, 6.5, 0.0], [1.0, -1.4, 7.5]])
+    pos = None
+    for _ in range(100):
+        s = rng.uniform(0, 1, (10, 3))
+        p = s @ cell
+        ii, jj, d = O.entries(p, cell, (1, 1, 1), 1.2)
+        if len(ii) == 0:
+            prm = O.Params(r_pot=9.0, r_cn=4.5)
+            if _min_gap_to_cutoffs(p, cell, (1, 1, 1), prm) > 1e-3:
+                pos = p
+                break
+    assert pos is not None
+    types = rng.integers(0, 5, 10).astype(np.int32)
+    res = O.d3(pos, types, cell, (1, 1, 1), tab, prm)
+    fd = _fd_forces(pos, types, cell, (1, 1, 1), tab, prm)
+    scale = np.abs(res["forces"]).max()
+    for a, f in fd.items():
+        assert f == pytest.approx(res["forces"][a], abs=1e-8 + 1e-7 * scale)
+    assert np.abs(res["forces"].sum(0)).max() < 1e-12 * max(1.0, scale) * 10
+
+
+def _strained(pos, cell, eps):
+    F = np.eye(3) + eps
+    return pos @ F.T, cell @ F.T
+
+
+def test_virial_matches_strain_derivative():
+    """Eq. 7 summed over atoms equals -dE/d(strain): central differences of
+    E under a homogeneous deformation r -> (1 + eps) r of positions and
+    lattice vectors, per tensor component, in a periodic triclinic cell."""
+    tab = _table()
+    rng = np.random.default_rng(8)
+    cell = np.array([[8.0, 0.0, 0.0], [1.5, 7.2, 0.0], [-0.8, 1.1, 8.4]])
+    prm = O.Params(r_pot=8.5, r_cn=4.0)
+    for _ in range(200):
+        s = rng.uniform(0, 1, (12, 3))
+        pos = s @ cell
+        ii, jj, d = O.entries(pos, cell, (1, 1, 1), 1.2)
+        if len(ii) == 0 and _min_gap_to_cutoffs(pos, cell, (1, 1, 1), prm) > 2e-3:
+            break
+    types = rng.integers(0, 5, 12).astype(np.int32)
+    res = O.d3(pos, types, cell, (1, 1, 1), tab, prm)
+    h = 1e-6
+    W = res["virial"]
+    assert W == pytest.approx(W.T, abs=1e-13 * np.abs(W).max())
+    for a in range(3):
+        for b in range(3):
+            e = np.zeros((3, 3))
+            e[a, b] = h
+            p1, c1 = _strained(pos, cell, e)
+            p2, c2 = _strained(pos, cell, -e)
+            ep = O.energy_only(p1, types, c1, (1, 1, 1), tab, prm)
+            em = O.energy_only(p2, types, c2, (1, 1, 1), tab, prm)
+            assert -(ep - em) / (2 * h) == pytest.approx(
+                W[a, b], abs=1e-7 * np.abs(W).max())
+
+
+def test_virial_equals_r_cross_f_for_cluster():
+    """For a finite cluster the virial is sum_i r_i (x) F_i."""
+    tab = _table()
+    c = synth.cluster(30, 5.0, seed=2)
+    res = O.d3(c["pos"], c["types"], None, (0, 0, 0), tab, O.Params())
+    assert res["virial"] == pytest.approx(c["pos"].T @ res["forces"],
+                                          abs=1e-13)
+
+
+# ------------------------------------------------------ invariances -------
+
+def test_invariances_translation_rotation_permutation():
+    """E, W invariant and F covariant under rigid translation (with atoms
+    leaving the cell), rotation of cell and positions, and relabelling of
+    the atoms; sum of forces is zero."""
+    tab = _table()
+    m = synth.mof_like(300, seed=4)
+    cell, pbc = m["cell"], m["pbc"]
+    prm = O.Params(r_pot=9.0, r_cn=5.0)
+    ref = O.d3(m["pos"], m["types"], cell, pbc, tab, prm)
+    assert np.abs(ref["forces"].sum(0)).max() < 1e-11
+    t = O.d3(m["pos"] + np.array([3.3, -17.0, 41.0]), m["types"], cell, pbc,
+             tab, prm)
+    assert t["energy"] == pytest.approx(ref["energy"], rel=1e-12)
+    assert t["forces"] == pytest.approx(ref["forces"], abs=1e-11)
+    th = 0.7
+    rot = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0],
+                    [0, 0, 1.0]]) @ np.array([[1, 0, 0], [0, np.cos(0.3), -np.sin(0.3)],
+                                              [0, np.sin(0.3), np.cos(0.3)]])
+    r = O.d3(m["pos"] @ rot.T, m["types"], cell @ rot.T, pbc, tab, prm)
+    assert r["energy"] == pytest.approx(ref["energy"], rel=1e-12)
+    assert r["forces"] == pytest.approx(ref["forces"] @ rot.T, abs=1e-11)
+    assert r["virial"] == pytest.approx(rot @ ref["virial"] @ rot.T, abs=1e-10)
+    perm = np.random.default_rng(1).permutation(300)
+    p = O.d3(m["pos"][perm], m["types"][perm], cell, pbc, tab, prm)
+    assert p["energy"] == pytest.approx(ref["energy"], rel=1e-12)
+    assert p["forces"] == pytest.approx(ref["forces"][perm], abs=1e-12)
+
+
+def test_supercell_replication():
+    """Replicating a periodic cell 2x2 in-plane leaves the energy per atom,
+    the virial per atom and the force on each copy of an atom unchanged
+    (images handled consistently, cutoff wider than the small cell)."""
+    tab = _table()
+    g = synth.bilayer_graphene(3, 3, seed=9)
+    cell = g["cell"]
+    reps = []
+    for ia in range(2):
+        for ib in range(2):
+            reps.append(g["pos"] + ia * cell[0] + ib * cell[1])
+    pos2 = np.concatenate(reps)
+    cell2 = cell.copy()
+    cell2[0] *= 2
+    cell2[1] *= 2
+    t2 = np.tile(g["types"], 4)
+    a = R.d3(g["pos"], g["types"], cell, g["pbc"], tab)
+    b = R.d3(pos2, t2, cell2, g["pbc"], tab)
+    n = g["pos"].shape[0]
+    assert b["energy"] / (4 * n) == pytest.approx(a["energy"] / n, rel=1e-12)
+    assert b["virial"] / 4 == pytest.approx(a["virial"], rel=1e-11, abs=1e-14)
+    for k in range(4):
+        assert b["forces"][k * n:(k + 1) * n] == pytest.approx(a["forces"],
+                                                               abs=1e-14)
+
+
+def test_perfect_ab_bilayer_symmetry():
+    """A perfect AB bilayer has no in-plane forces (every atom sits on a
+    site of threefold symmetry) and an in-plane isotropic virial."""
+    tab = _table()
+    g = synth.bilayer_graphene(6, 6, jitter=0.0)
+    res = R.d3(g["pos"], g["types"], g["cell"], g["pbc"], tab)
+    assert np.abs(res["forces"][:, :2]).max() < 1e-14
+    W = res["virial"]
+    assert W[0, 0] == pytest.approx(W[1, 1], rel=1e-12)
+    assert abs(W[0, 1]) < 1e-12 * abs(W[0, 0])
+    # the two layers attract: equal and opposite z forces
+    fz = res["forces"][:, 2]
+    z = g["pos"][:, 2]
+    top = z > z.mean()
+    assert fz[top].sum() == pytest.approx(-fz[~top].sum(), rel=1e-12)
+    assert fz[top].sum() < 0.0
+
+
+def test_single_atom_cells():
+    """One atom in a large box has no entries (E = 0); one atom in a small
+    periodic box interacts with its own images: E < 0 and zero force."""
+    tab = _table()
+    big = np.eye(3) * 30.0
+    r = O.d3(np.array([[1.0, 2.0, 3.0]]), np.array([2]), big, (1, 1, 1), tab)
+    assert r["energy"] == 0.0 and np.all(r["forces"] == 0.0)
+    small = np.eye(3) * 4.0
+    r = O.d3(np.array([[1.0, 2.0, 3.0]]), np.array([2]), small, (1, 1, 1), tab)
+    assert r["energy"] < 0.0 and np.abs(r["forces"]).max() < 1e-15
+    assert r["cn"][0] > 0.0
+
+
+# ------------------------------------------------------ oracle<->oracle ---
+
+def test_c_oracle_matches_numpy_oracle():
+    """The C oracle (used at larger sizes and for the CPU baseline) agrees
+    with the NumPy oracle on graphene, a MOF-like cube and a tiny
+    triclinic cell with many images."""
+    tab = _table()
+    cases = [synth.bilayer_graphene(), synth.mof_like(500, seed=5)]
+    cell = np.array([[5.0, 0.0, 0.0], [2.0, 4.6, 0.0], [0.5, 0.7, 5.3]])
+    s = np.random.default_rng(2).uniform(0, 1, (4, 3))
+    cases.append({"pos": s @ cell, "types": np.array([0, 1, 2, 4], np.int32),
+                  "cell": cell, "pbc": np.array([1, 1, 1])})
+    for c in cases:
+        a = O.d3(c["pos"], c["types"], c["cell"], c["pbc"], tab)
+        b = R.d3(c["pos"], c["types"], c["cell"], c["pbc"], tab)
+        assert b["energy"] == pytest.approx(a["energy"], rel=1e-12)
+        for k in ("forces", "virial", "atom_energy", "cn", "dedn"):
+            sc = max(np.abs(a[k]).max(), 1e-30)
+            # dE/dn sums terms of both signs: looser relative bound
+            tol = 1e-10 if k == "dedn" else 1e-12
+            assert np.abs(a[k] - b[k]).max() <= tol * sc, k
+
+
+def test_sampled_mode_matches_full():
+    """The per-atom neighbourhood evaluation used at 10^5-10^6 atoms gives
+    the same force, site energy, CN and dE/dn as the full evaluation."""
+    tab = _table()
+    m = synth.mof_like(900, seed=6)
+    full = R.d3(m["pos"], m["types"], m["cell"], m["pbc"], tab)
+    idx = [0, 11, 450, 899]
+    s = O.sampled(m["pos"], m["types"], m["cell"], m["pbc"], tab, idx)
+    sc = np.abs(full["forces"]).max()
+    assert np.abs(s["forces"] - full["forces"][idx]).max() < 1e-12 * sc
+    assert s["atom_energy"] == pytest.approx(full["atom_energy"][idx], rel=1e-11)
+    assert s["cn"] == pytest.approx(full["cn"][idx], rel=1e-12)
+    assert s["dedn"] == pytest.approx(full["dedn"][idx], rel=1e-10, abs=1e-14)
