@@ -1,0 +1,620 @@
+// Host side of the C ABI declared in include/d3.h: argument validation,
+// table conversion, bin geometry, device scratch and launch sequencing.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "d3_ctx.h"
+
+namespace d3 {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(D3_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int ensure_bytes(void** p, size_t* have, size_t need)
+{
+    if (need == 0) need = 256;
+    if (*p && *have >= need) return D3_OK;
+    if (*p) {
+        hipError_t e = hipFree(*p);
+        *p = nullptr;
+        *have = 0;
+        if (e != hipSuccess) return hip_fail(e, "hipFree");
+    }
+    hipError_t e = hipMalloc(p, need);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(e, "hipMalloc");
+    }
+    *have = need;
+    return D3_OK;
+}
+
+void release(Buf& b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+static const double HARTREE_EV = 27.211386245988;
+static const double BOHR_ANG = 0.529177210903;
+
+static void inv3(const double* m, double* o)
+{
+    const double det = m[0] * (m[4] * m[8] - m[5] * m[7]) -
+                       m[1] * (m[3] * m[8] - m[5] * m[6]) +
+                       m[2] * (m[3] * m[7] - m[4] * m[6]);
+    o[0] = (m[4] * m[8] - m[5] * m[7]) / det;
+    o[1] = (m[2] * m[7] - m[1] * m[8]) / det;
+    o[2] = (m[1] * m[5] - m[2] * m[4]) / det;
+    o[3] = (m[5] * m[6] - m[3] * m[8]) / det;
+    o[4] = (m[0] * m[8] - m[2] * m[6]) / det;
+    o[5] = (m[2] * m[3] - m[0] * m[5]) / det;
+    o[6] = (m[3] * m[7] - m[4] * m[6]) / det;
+    o[7] = (m[1] * m[6] - m[0] * m[7]) / det;
+    o[8] = (m[0] * m[4] - m[1] * m[3]) / det;
+}
+
+// Bin layout for list cutoff rlist: nb_k bins along lattice vector k,
+// each at least rlist / BIN_DIV wide (measured between lattice planes),
+// stencil reach ceil(rlist / width) bins, and the image translations the
+// stencil can reach on periodic axes.
+int make_geo(const double* cell, const int32_t* pbc, double rlist, int64_t n,
+             Geo& g, std::vector<double4>& imgs)
+{
+    double la[3];
+    for (int k = 0; k < 3; k++)
+        la[k] = std::sqrt(cell[3 * k] * cell[3 * k] + cell[3 * k + 1] * cell[3 * k + 1] +
+                          cell[3 * k + 2] * cell[3 * k + 2]);
+    const double det = cell[0] * (cell[4] * cell[8] - cell[5] * cell[7]) -
+                       cell[1] * (cell[3] * cell[8] - cell[5] * cell[6]) +
+                       cell[2] * (cell[3] * cell[7] - cell[4] * cell[6]);
+    if (!std::isfinite(det) || la[0] == 0.0 || la[1] == 0.0 || la[2] == 0.0 ||
+        std::fabs(det) <= 1e-10 * la[0] * la[1] * la[2])
+        return fail(D3_ERR_CELL, "singular or non-finite cell (det=%g)", det);
+    std::memcpy(g.H, cell, sizeof(g.H));
+    inv3(cell, g.Hinv);
+    const double vol = std::fabs(det);
+    const double target = rlist / BIN_DIV;
+    double h[3];
+    long nb[3];
+    for (int k = 0; k < 3; k++) {
+        g.pbc[k] = pbc[k] ? 1 : 0;
+        const double* u = cell + 3 * ((k + 1) % 3);
+        const double* v = cell + 3 * ((k + 2) % 3);
+        const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2],
+                     cz = u[0] * v[1] - u[1] * v[0];
+        h[k] = vol / std::sqrt(cx * cx + cy * cy + cz * cz);
+        nb[k] = (long)std::floor(h[k] / target);
+        nb[k] = std::max(1L, std::min(nb[k], 2048L));
+    }
+    while (nb[0] * nb[1] * nb[2] > (1L << 24)) {  // keep the bin table modest
+        int k = 0;
+        for (int q = 1; q < 3; q++)
+            if (nb[q] > nb[k]) k = q;
+        nb[k] = (nb[k] + 1) / 2;
+    }
+    for (int k = 0; k < 3; k++) {
+        const double width = h[k] / (double)nb[k];
+        long reach = (long)std::ceil(rlist / width * (1.0 + 1e-12));
+        if (!g.pbc[k] && reach > nb[k] - 1) reach = nb[k] - 1;
+        if (reach > 4096)
+            return fail(D3_ERR_CELL, "cutoff spans %ld cells along lattice vector %d", reach, k);
+        g.nb[k] = (int)nb[k];
+        g.reach[k] = (int)reach;
+        g.timg[k] = g.pbc[k] ? (int)((reach + nb[k] - 1) / nb[k]) : 0;
+    }
+    g.nbins = (int)(nb[0] * nb[1] * nb[2]);
+    const long nimg = (long)(2 * g.timg[0] + 1) * (2 * g.timg[1] + 1) * (2 * g.timg[2] + 1);
+    int bits = 0;
+    while ((1L << bits) < nimg) bits++;
+    if (n > 0 && ((uint64_t)(n - 1) << bits) >= (1ull << 32))
+        return fail(D3_ERR_CELL,
+                    "%lld atoms x %ld periodic images exceed the 32-bit list encoding",
+                    (long long)n, nimg);
+    g.n_img = (int)nimg;
+    g.img_bits = bits;
+    imgs.resize(nimg);
+    int c = 0;
+    for (int t0 = -g.timg[0]; t0 <= g.timg[0]; t0++)
+        for (int t1 = -g.timg[1]; t1 <= g.timg[1]; t1++)
+            for (int t2 = -g.timg[2]; t2 <= g.timg[2]; t2++) {
+                double T[3];
+                for (int m = 0; m < 3; m++)
+                    T[m] = t0 * cell[m] + t1 * cell[3 + m] + t2 * cell[6 + m];
+                imgs[c++] = make_double4(T[0], T[1], T[2], 0.0);
+            }
+    return D3_OK;
+}
+
+static bool same_geometry(const d3_ctx* c, int64_t n, const double* cell, const int32_t* pbc)
+{
+    if (!c->built || c->n != n) return false;
+    for (int k = 0; k < 9; k++)
+        if (c->cell[k] != cell[k]) return false;
+    for (int k = 0; k < 3; k++)
+        if ((c->geo.pbc[k] != 0) != (pbc[k] != 0)) return false;
+    return true;
+}
+
+#define HIPCHK(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+#define D3CHK(call)                 \
+    do {                            \
+        int r_ = (call);            \
+        if (r_ != D3_OK) return r_; \
+    } while (0)
+
+int alloc_atoms(d3_ctx* c, int64_t n)
+{
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    D3CHK(ensure(c->bin_of, N * sizeof(int)));
+    D3CHK(ensure(c->shift, N * sizeof(double4)));
+    D3CHK(ensure(c->perm, N * sizeof(int)));
+    D3CHK(ensure(c->bin_s, N * sizeof(int)));
+    D3CHK(ensure(c->pos_s, N * sizeof(double4)));
+    D3CHK(ensure(c->shift_s, N * sizeof(double4)));
+    D3CHK(ensure(c->ref_s, N * sizeof(double4)));
+    D3CHK(ensure(c->type_copy, N * sizeof(int32_t)));
+    D3CHK(ensure(c->cn, N * sizeof(double)));
+    D3CHK(ensure(c->cnf, N * sizeof(float)));
+    D3CHK(ensure(c->w, N * MAXREF * sizeof(double)));
+    D3CHK(ensure(c->wd, N * MAXREF * sizeof(double)));
+    D3CHK(ensure(c->G, N * sizeof(double)));
+    D3CHK(ensure(c->Fp, N * 3 * sizeof(double)));
+    D3CHK(ensure(c->U, N * sizeof(double)));
+    D3CHK(ensure(c->cnt_p, N * sizeof(int)));
+    D3CHK(ensure(c->cnt_c, N * sizeof(int)));
+    const size_t nw = (size_t)pass_waves((int)n);
+    D3CHK(ensure(c->vpart, nw * 6 * sizeof(double)));
+    D3CHK(ensure(c->vpart2, nw * 6 * sizeof(double)));
+    return D3_OK;
+}
+
+int alloc_proj(d3_ctx* c, int mode)
+{
+    const size_t N = (size_t)(c->n > 0 ? c->n : 1);
+    const size_t m = (size_t)c->n_elem * N * MAXREF;
+    if (mode == D3_MODE_PREC_F32) return ensure(c->Pf, m * sizeof(float));
+    return ensure(c->P, m * sizeof(double));
+}
+
+// Binning, counting sort and list construction on stream s.
+int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists,
+              hipStream_t s)
+{
+    const int n = (int)c->n;
+    const Geo& g = c->geo;
+    HIPCHK(hipMemsetAsync(c->count.p, 0, (size_t)g.nbins * sizeof(int), s));
+    HIPCHK(hipMemsetAsync(c->fill.p, 0, (size_t)g.nbins * sizeof(int), s));
+    launch_bin(n, pos, type, c->n_elem, g, c->bin_of.as<int>(), c->shift.as<double4>(),
+               c->count.as<int>(), c->status.as<int>(), s);
+    launch_scan(g.nbins, c->count.as<int>(), c->bin_start.as<int>(), c->scan_tmp.as<int>(), s);
+    launch_scatter(n, c->bin_of.as<int>(), c->bin_start.as<int>(), c->fill.as<int>(),
+                   c->perm.as<int>(), s);
+    launch_binsort(g.nbins, c->bin_start.as<int>(), c->perm.as<int>(), c->bin_s.as<int>(), s);
+    launch_gather_build(n, pos, type, c->n_elem, c->perm.as<int>(), c->shift.as<double4>(),
+                        c->pos_s.as<double4>(), c->shift_s.as<double4>(),
+                        c->ref_s.as<double4>(), s);
+    HIPCHK(hipGetLastError());
+    const double rp = c->prm.r_pot + c->prm.skin, rcn = c->prm.r_cn + c->prm.skin;
+    if (size_lists) {
+        HIPCHK(hipMemsetAsync(c->maxcnt.p, 0, 8 * sizeof(int), s));
+        launch_list(n, c->pos_s.as<double4>(), c->bin_s.as<int>(), c->bin_start.as<int>(), g,
+                    c->img_tab.as<double4>(), rp * rp, rcn * rcn, nullptr, c->cnt_p.as<int>(), 0,
+                    nullptr, c->cnt_c.as<int>(), 0, 1, c->maxcnt.as<int>(),
+                    c->status.as<int>(), s);
+        HIPCHK(hipGetLastError());
+        int mc[8];
+        HIPCHK(hipMemcpyAsync(mc, c->maxcnt.p, sizeof(mc), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        // headroom for later rebuilds of the same geometry (MD)
+        c->cap_p = std::max(1, mc[0] + std::max(16, mc[0] / 8));
+        c->cap_c = std::max(1, mc[1] + std::max(16, mc[1] / 8));
+        c->cap_p = (c->cap_p + 3) & ~3;
+        c->cap_c = (c->cap_c + 3) & ~3;
+        const size_t N = (size_t)(n > 0 ? n : 1);
+        D3CHK(ensure(c->list_p, N * c->cap_p * sizeof(uint32_t)));
+        D3CHK(ensure(c->list_c, N * c->cap_c * sizeof(uint32_t)));
+    }
+    HIPCHK(hipMemsetAsync(c->maxcnt.p, 0, 8 * sizeof(int), s));
+    launch_list(n, c->pos_s.as<double4>(), c->bin_s.as<int>(), c->bin_start.as<int>(), g,
+                c->img_tab.as<double4>(), rp * rp, rcn * rcn, c->list_p.as<uint32_t>(),
+                c->cnt_p.as<int>(), c->cap_p, c->list_c.as<uint32_t>(), c->cnt_c.as<int>(),
+                c->cap_c, 0, c->maxcnt.as<int>(), c->status.as<int>(), s);
+    HIPCHK(hipGetLastError());
+    return D3_OK;
+}
+
+int read_status(d3_ctx* c, hipStream_t s, int* out)
+{
+    HIPCHK(hipMemcpyAsync(c->h_status, c->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *out = *c->h_status;
+    return D3_OK;
+}
+
+int status_code(int bits)
+{
+    if (bits & ST_SPECIES) return fail(D3_ERR_SPECIES, "a species index is outside [0, n_elem)");
+    if (bits & ST_NONFINITE) return fail(D3_ERR_INVALID_ARG, "non-finite atomic position");
+    if (bits & ST_CAPACITY) return fail(D3_ERR_CAPACITY, "neighbour list capacity exceeded");
+    if (bits & ST_STALE) return fail(D3_ERR_STALE, "an atom moved more than skin/2 since the last build");
+    return D3_OK;
+}
+
+// geometry-aware build used by d3_build_neighbors and by auto-rebuilds
+int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const double* cell,
+          const int32_t* pbc, hipStream_t s)
+{
+    const bool same = same_geometry(c, n, cell, pbc);
+    if (!same) {
+        Geo g;
+        std::vector<double4> imgs;
+        const double rlist = std::max(c->prm.r_pot, c->prm.r_cn) + c->prm.skin;
+        D3CHK(make_geo(cell, pbc, rlist, n, g, imgs));
+        c->n = n;
+        c->geo = g;
+        std::memcpy(c->cell, cell, sizeof(c->cell));
+        D3CHK(alloc_atoms(c, n));
+        D3CHK(ensure(c->count, (size_t)g.nbins * sizeof(int)));
+        D3CHK(ensure(c->fill, (size_t)g.nbins * sizeof(int)));
+        D3CHK(ensure(c->bin_start, ((size_t)g.nbins + 1) * sizeof(int)));
+        D3CHK(ensure(c->scan_tmp, ((size_t)g.nbins / 1024 + 4) * sizeof(int)));
+        D3CHK(ensure(c->img_tab, imgs.size() * sizeof(double4)));
+        HIPCHK(hipMemcpyAsync(c->img_tab.p, imgs.data(), imgs.size() * sizeof(double4),
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        c->built = false;
+    }
+    if (n > 0 && type != c->type_copy.as<int32_t>())
+        HIPCHK(hipMemcpyAsync(c->type_copy.p, type, (size_t)n * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, s));
+    D3CHK(run_build(c, pos, c->type_copy.as<int32_t>(), !same, s));
+    c->built = true;
+    c->fresh_build = true;
+    c->last_stream = s;
+    return D3_OK;
+}
+
+int update_positions(d3_ctx* c, const double* pos, hipStream_t s)
+{
+    const double hs = 0.5 * c->prm.skin;
+    launch_update((int)c->n, pos, c->perm.as<int>(), c->shift_s.as<double4>(),
+                  c->ref_s.as<double4>(), c->pos_s.as<double4>(), hs * hs,
+                  c->status.as<int>(), s);
+    HIPCHK(hipGetLastError());
+    return D3_OK;
+}
+
+int coordination(d3_ctx* c, int mode, hipStream_t s)
+{
+    D3CHK(alloc_proj(c, mode));
+    const Geo& g = c->geo;
+    launch_cn(mode, (int)c->n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.img_bits,
+              c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, c->d_tab.as<ElemTab>(),
+              c->d_c6.as<double>(), c->prm.r_cn * c->prm.r_cn, c->cn.as<double>(),
+              c->w.as<double>(), c->wd.as<double>(), c->P.as<double>(), c->Pf.as<float>(),
+              c->cnf.as<float>(), s);
+    HIPCHK(hipGetLastError());
+    return D3_OK;
+}
+
+}  // namespace d3
+
+using namespace d3;
+
+extern "C" {
+
+const char* d3_last_error(void) { return g_err.c_str(); }
+
+int d3_create(const d3_params* prm, const d3_table* tab, d3_ctx** out)
+{
+    if (!out) return fail(D3_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!prm || !tab) return fail(D3_ERR_INVALID_ARG, "params or table is NULL");
+    if (!(prm->r_pot > 0.0) || !(prm->r_cn > 0.0) || !(prm->skin >= 0.0) ||
+        !std::isfinite(prm->r_pot) || !std::isfinite(prm->r_cn) || !std::isfinite(prm->skin))
+        return fail(D3_ERR_INVALID_ARG, "cutoffs must be positive and finite, skin >= 0");
+    if (!std::isfinite(prm->s6) || !std::isfinite(prm->s8) || !std::isfinite(prm->a1) ||
+        !std::isfinite(prm->a2))
+        return fail(D3_ERR_INVALID_ARG, "non-finite damping parameter");
+    if (prm->mode < D3_MODE_PLAIN_F64 || prm->mode > D3_MODE_SURROGATE)
+        return fail(D3_ERR_INVALID_ARG, "unknown mode %d", prm->mode);
+    const int ne = tab->n_elem;
+    if (ne < 1 || ne > MAXELEM) return fail(D3_ERR_INVALID_ARG, "n_elem=%d outside 1..%d", ne, MAXELEM);
+    if (!tab->n_ref || !tab->cn_ref || !tab->c6_ref || !tab->rcov || !tab->r2r4)
+        return fail(D3_ERR_INVALID_ARG, "table array is NULL");
+    for (int e = 0; e < ne; e++) {
+        if (tab->n_ref[e] < 1 || tab->n_ref[e] > MAXREF)
+            return fail(D3_ERR_INVALID_ARG, "n_ref[%d]=%d outside 1..%d", e, tab->n_ref[e], MAXREF);
+        if (!(tab->rcov[e] >= 0.0) || !(tab->r2r4[e] >= 0.0) || !std::isfinite(tab->rcov[e]) ||
+            !std::isfinite(tab->r2r4[e]))
+            return fail(D3_ERR_INVALID_ARG, "rcov/r2r4 of element %d invalid", e);
+        for (int a = 0; a < tab->n_ref[e]; a++)
+            if (!std::isfinite(tab->cn_ref[e * MAXREF + a]))
+                return fail(D3_ERR_INVALID_ARG, "cn_ref of element %d not finite", e);
+    }
+    for (int e = 0; e < ne; e++)
+        for (int f = 0; f < ne; f++)
+            for (int a = 0; a < tab->n_ref[e]; a++)
+                for (int b = 0; b < tab->n_ref[f]; b++) {
+                    const double x = tab->c6_ref[((e * ne + f) * MAXREF + a) * MAXREF + b];
+                    const double y = tab->c6_ref[((f * ne + e) * MAXREF + b) * MAXREF + a];
+                    if (!std::isfinite(x) || x != y)
+                        return fail(D3_ERR_INVALID_ARG,
+                                    "c6_ref not symmetric or not finite at (%d,%d,%d,%d)", e, f, a, b);
+                }
+    d3_ctx* c = new d3_ctx();
+    c->prm = *prm;
+    c->n_elem = ne;
+    HIPCHK(hipGetDevice(&c->device));
+    ElemTab et;
+    std::memset(&et, 0, sizeof(et));
+    et.n_elem = ne;
+    std::vector<double> c6((size_t)MAXELEM * MAXELEM * MAXREF * MAXREF, 0.0);
+    std::vector<double4> pc((size_t)MAXELEM * MAXELEM, make_double4(0, 0, 0, 0));
+    const double conv = HARTREE_EV * std::pow(BOHR_ANG, 6);
+    for (int e = 0; e < ne; e++) {
+        et.n_ref[e] = tab->n_ref[e];
+        for (int a = 0; a < MAXREF; a++)
+            et.cn_ref[e * MAXREF + a] = a < tab->n_ref[e] ? tab->cn_ref[e * MAXREF + a] : 0.0;
+        et.rcov[e] = tab->rcov[e];
+        for (int f = 0; f < ne; f++) {
+            for (int a = 0; a < tab->n_ref[e]; a++)
+                for (int b = 0; b < tab->n_ref[f]; b++)
+                    c6[((size_t)(e * MAXELEM + f) * MAXREF + a) * MAXREF + b] =
+                        tab->c6_ref[((e * ne + f) * MAXREF + a) * MAXREF + b] * conv;
+            const double r0sq = 3.0 * tab->r2r4[e] * tab->r2r4[f] * BOHR_ANG * BOHR_ANG;
+            const double rd = prm->a1 * std::sqrt(r0sq) + prm->a2;
+            const double rd2 = rd * rd, rd6 = rd2 * rd2 * rd2;
+            pc[e * MAXELEM + f] = make_double4(rd6, rd6 * rd2, r0sq, 0.0);
+        }
+    }
+    c->h_c6 = c6;
+    c->h_tab = et;
+    for (int e = 0; e < ne; e++) c->h_r2r4[e] = tab->r2r4[e];
+    int r;
+    if ((r = ensure(c->d_tab, sizeof(ElemTab))) ||
+        (r = ensure(c->d_c6, c6.size() * sizeof(double))) ||
+        (r = ensure(c->d_pc, pc.size() * sizeof(double4))) ||
+        (r = ensure(c->status, 256)) || (r = ensure(c->maxcnt, 256))) {
+        d3_destroy(c);
+        return r;
+    }
+    hipError_t e1 = hipMemcpy(c->d_tab.p, &et, sizeof(et), hipMemcpyHostToDevice);
+    hipError_t e2 = hipMemcpy(c->d_c6.p, c6.data(), c6.size() * sizeof(double), hipMemcpyHostToDevice);
+    hipError_t e3 = hipMemcpy(c->d_pc.p, pc.data(), pc.size() * sizeof(double4), hipMemcpyHostToDevice);
+    hipError_t e4 = hipMemset(c->status.p, 0, 256);
+    hipError_t e5 = hipHostMalloc((void**)&c->h_status, 64, hipHostMallocDefault);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess ||
+        e5 != hipSuccess) {
+        hipError_t e = e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3 != hipSuccess ? e3
+                     : e4 != hipSuccess ? e4 : e5;
+        d3_destroy(c);
+        return hip_fail(e, "d3_create upload");
+    }
+    *out = c;
+    return D3_OK;
+}
+
+void d3_destroy(d3_ctx* c)
+{
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    for (Buf* b : c->all_buffers()) release(*b);
+    if (c->h_status) (void)hipHostFree(c->h_status);
+    surrogate_free(c);
+    delete c;
+}
+
+int d3_set_mode(d3_ctx* c, int32_t mode)
+{
+    if (!c) return fail(D3_ERR_INVALID_ARG, "ctx is NULL");
+    if (mode < D3_MODE_PLAIN_F64 || mode > D3_MODE_SURROGATE)
+        return fail(D3_ERR_INVALID_ARG, "unknown mode %d", mode);
+    c->prm.mode = mode;
+    return D3_OK;
+}
+
+int d3_build_neighbors(d3_ctx* c, int64_t n, const double* pos, const int32_t* type,
+                       const double* cell, const int32_t* pbc, void* stream)
+{
+    if (!c) return fail(D3_ERR_INVALID_ARG, "ctx is NULL");
+    if (n < 0 || n > (int64_t)INT32_MAX / 2) return fail(D3_ERR_INVALID_ARG, "n=%lld out of range", (long long)n);
+    if (n > 0 && (!pos || !type)) return fail(D3_ERR_INVALID_ARG, "pos or type is NULL");
+    if (!cell || !pbc) return fail(D3_ERR_INVALID_ARG, "cell or pbc is NULL");
+    for (int k = 0; k < 9; k++)
+        if (!std::isfinite(cell[k])) return fail(D3_ERR_CELL, "non-finite cell");
+    for (int k = 0; k < 3; k++)
+        if (pbc[k] != 0 && pbc[k] != 1) return fail(D3_ERR_INVALID_ARG, "pbc[%d]=%d not 0/1", k, pbc[k]);
+    if (((uintptr_t)pos & 7) || ((uintptr_t)type & 3))
+        return fail(D3_ERR_INVALID_ARG, "misaligned pos or type pointer");
+    hipStream_t s = (hipStream_t)stream;
+    return build(c, n, pos, type, cell, pbc, s);
+}
+
+int d3_coordination(d3_ctx* c, const double* pos, double* cn_out, void* stream)
+{
+    if (!c) return fail(D3_ERR_INVALID_ARG, "ctx is NULL");
+    if (!c->built) return fail(D3_ERR_STATE, "d3_coordination before d3_build_neighbors");
+    if (c->n > 0 && !pos) return fail(D3_ERR_INVALID_ARG, "pos is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (c->n == 0) return D3_OK;
+    D3CHK(update_positions(c, pos, s));
+    const int mode = c->prm.mode == D3_MODE_PREC_F32 ? D3_MODE_PREC_F32 : D3_MODE_PLAIN_F64;
+    D3CHK(coordination(c, mode, s));
+    if (cn_out) {
+        launch_scatter_out((int)c->n, c->cn.as<double>(), c->perm.as<int>(), cn_out, s);
+        HIPCHK(hipGetLastError());
+    }
+    return D3_OK;
+}
+
+int d3_energy_forces_virial(d3_ctx* c, const double* pos, double* energy, double* forces,
+                            double* virial, double* atom_energy, uint32_t flags, void* stream)
+{
+    if (!c) return fail(D3_ERR_INVALID_ARG, "ctx is NULL");
+    if (!c->built) return fail(D3_ERR_STATE, "d3_energy_forces_virial before d3_build_neighbors");
+    if (!energy) return fail(D3_ERR_INVALID_ARG, "energy is NULL");
+    if (c->n > 0 && !pos) return fail(D3_ERR_INVALID_ARG, "pos is NULL");
+    if (flags & ~(D3_ACCUMULATE | D3_AUTO_REBUILD)) return fail(D3_ERR_INVALID_ARG, "unknown flags");
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    const int acc = (flags & D3_ACCUMULATE) ? 1 : 0;
+    const int n = (int)c->n;
+    if (n == 0) {
+        if (!acc) {
+            HIPCHK(hipMemsetAsync(energy, 0, sizeof(double), s));
+            if (virial) HIPCHK(hipMemsetAsync(virial, 0, 9 * sizeof(double), s));
+        }
+        return D3_OK;
+    }
+    D3CHK(update_positions(c, pos, s));
+    if (flags & D3_AUTO_REBUILD) {
+        int st = 0;
+        D3CHK(read_status(c, s, &st));
+        if (st & (ST_STALE | ST_CAPACITY)) {
+            const int keep = st & ~(ST_STALE | ST_CAPACITY);
+            HIPCHK(hipMemsetAsync(c->status.p, 0, sizeof(int), s));
+            if (keep) {
+                *c->h_status = keep;
+                HIPCHK(hipMemcpyAsync(c->status.p, c->h_status, sizeof(int), hipMemcpyHostToDevice, s));
+            }
+            D3CHK(rebuild_grow(c, pos, s));
+        }
+    }
+    const int mode = c->prm.mode;
+    D3CHK(evaluate(c, mode, energy, forces, virial, atom_energy, acc, s));
+    return D3_OK;
+}
+
+int d3_status(d3_ctx* c)
+{
+    if (!c) return fail(D3_ERR_INVALID_ARG, "ctx is NULL");
+    int st = 0;
+    D3CHK(read_status(c, c->last_stream, &st));
+    HIPCHK(hipMemsetAsync(c->status.p, 0, sizeof(int), c->last_stream));
+    HIPCHK(hipStreamSynchronize(c->last_stream));
+    return status_code(st);
+}
+
+int d3_list_stats(d3_ctx* c, double* out)
+{
+    if (!c || !out) return fail(D3_ERR_INVALID_ARG, "NULL argument");
+    if (!c->built) return fail(D3_ERR_STATE, "no build yet");
+    int mc[8];
+    HIPCHK(hipMemcpyAsync(mc, c->maxcnt.p, sizeof(mc), hipMemcpyDeviceToHost, c->last_stream));
+    HIPCHK(hipStreamSynchronize(c->last_stream));
+    unsigned long long sp, sc;
+    std::memcpy(&sp, &mc[2], 8);
+    std::memcpy(&sc, &mc[4], 8);
+    const double n = c->n > 0 ? (double)c->n : 1.0;
+    out[0] = mc[0];
+    out[1] = (double)sp / n;
+    out[2] = mc[1];
+    out[3] = (double)sc / n;
+    out[4] = c->geo.nbins;
+    out[5] = c->geo.n_img;
+    return D3_OK;
+}
+
+}  // extern "C"
+
+namespace d3 {
+
+// rebuild from the current positions (auto-rebuild path); grows the lists
+// if the previous build overflowed
+int rebuild_grow(d3_ctx* c, const double* pos, hipStream_t s)
+{
+    double cell[9];
+    int32_t pbc[3];
+    std::memcpy(cell, c->cell, sizeof(cell));
+    for (int k = 0; k < 3; k++) pbc[k] = c->geo.pbc[k];
+    D3CHK(build(c, c->n, pos, c->type_copy.as<int32_t>(), cell, pbc, s));
+    int st = 0;
+    D3CHK(read_status(c, s, &st));
+    if (st & ST_CAPACITY) {
+        int mc[8];
+        HIPCHK(hipMemcpyAsync(mc, c->maxcnt.p, sizeof(mc), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        c->cap_p = std::max(c->cap_p, mc[0] + std::max(16, mc[0] / 4));
+        c->cap_c = std::max(c->cap_c, mc[1] + std::max(16, mc[1] / 4));
+        c->cap_p = (c->cap_p + 3) & ~3;
+        c->cap_c = (c->cap_c + 3) & ~3;
+        const size_t N = (size_t)c->n;
+        D3CHK(ensure(c->list_p, N * c->cap_p * sizeof(uint32_t)));
+        D3CHK(ensure(c->list_c, N * c->cap_c * sizeof(uint32_t)));
+        HIPCHK(hipMemsetAsync(c->status.p, 0, sizeof(int), s));
+        D3CHK(run_build(c, pos, c->type_copy.as<int32_t>(), false, s));
+        D3CHK(read_status(c, s, &st));
+        if (st & ST_CAPACITY) return fail(D3_ERR_CAPACITY, "neighbour list capacity exceeded after regrow");
+    }
+    return D3_OK;
+}
+
+int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial,
+             double* atom_energy, int acc, hipStream_t s)
+{
+    const int n = (int)c->n;
+    const Geo& g = c->geo;
+    int cn_mode = mode == D3_MODE_PREC_F32 ? D3_MODE_PREC_F32 : D3_MODE_PLAIN_F64;
+    if (mode == D3_MODE_SURROGATE) {
+        if (!c->sur || !c->sur->trained)
+            return fail(D3_ERR_NOT_TRAINED, "surrogate mode before training or loading weights");
+        D3CHK(alloc_proj(c, D3_MODE_PREC_F32));
+        cn_mode = D3_MODE_PREC_F32;  // surrogate needs float CNs; exact fallback uses Pf
+    }
+    D3CHK(coordination(c, cn_mode, s));
+    PairScal sc;
+    sc.s6 = c->prm.s6;
+    sc.s8 = c->prm.s8;
+    sc.rp2 = c->prm.r_pot * c->prm.r_pot;
+    sc.rc2 = c->prm.r_cn * c->prm.r_cn;
+    if (mode == D3_MODE_SURROGATE) {
+        D3CHK(surrogate_pair(c, sc, s));
+    } else {
+        launch_pair(mode, n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.img_bits,
+                    c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p, c->d_tab.as<ElemTab>(),
+                    c->d_pc.as<double4>(), sc, c->w.as<double>(), c->wd.as<double>(),
+                    c->P.as<double>(), c->Pf.as<float>(), c->Fp.as<double>(), c->U.as<double>(),
+                    c->G.as<double>(), c->vpart.as<double>(), s);
+        HIPCHK(hipGetLastError());
+    }
+    launch_chain(mode == D3_MODE_PLAIN_F64 ? D3_MODE_PLAIN_F64 : D3_MODE_PREC_F32, n,
+                 c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.img_bits,
+                 c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, c->d_tab.as<ElemTab>(),
+                 sc.rc2, c->G.as<double>(), c->Fp.as<double>(), c->U.as<double>(),
+                 c->perm.as<int>(), forces, atom_energy, acc, c->vpart2.as<double>(), s);
+    HIPCHK(hipGetLastError());
+    launch_reduce(n, c->U.as<double>(), pass_waves(n), c->vpart.as<double>(),
+                  c->vpart2.as<double>(), energy, virial, acc, s);
+    HIPCHK(hipGetLastError());
+    return D3_OK;
+}
+
+}  // namespace d3

@@ -1,0 +1,101 @@
+// Host-side context of the library (opaque d3_ctx of the C ABI).
+#pragma once
+
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "d3_internal.h"
+
+namespace d3 {
+
+constexpr double BIN_DIV = 2.0;  // bins per list cutoff along each axis
+
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    template <class T>
+    T* as() const { return (T*)p; }
+};
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int ensure_bytes(void** p, size_t* have, size_t need);
+inline int ensure(Buf& b, size_t need) { return ensure_bytes(&b.p, &b.bytes, need); }
+void release(Buf& b);
+
+// learned C6 surrogate state (mlp.hip)
+struct Surrogate {
+    int n_pairs = 0;
+    bool trained = false;
+    float cn_hi = 0.0f;
+    Buf w32;       // FP32 master weights, n_pairs * D3_MLP_PARAMS
+    Buf stats;     // per pair: mean[3], scale[3] (FP32)
+    Buf adam_m, adam_v, grad;
+    Buf packed;    // inference pack (bf16 layer-2 weights + fp32 rest)
+    Buf samples;   // training inputs/targets
+    Buf loss;      // per-step losses
+    std::vector<float> h_w;  // host copy (get/set)
+};
+
+struct d3_ctx_impl;
+
+}  // namespace d3
+
+struct d3_ctx {
+    d3_params prm{};
+    int n_elem = 0;
+    int device = 0;
+    d3::ElemTab h_tab{};
+    std::vector<double> h_c6;
+    double h_r2r4[D3_MAX_ELEM] = {};
+    d3::Buf d_tab, d_c6, d_pc;
+    // geometry of the last build
+    int64_t n = 0;
+    double cell[9] = {};
+    d3::Geo geo{};
+    bool built = false;
+    bool fresh_build = false;
+    // cell-sorted data
+    d3::Buf bin_of, shift, count, fill, bin_start, scan_tmp, bin_s, perm;
+    d3::Buf pos_s, shift_s, ref_s, type_copy, img_tab;
+    // lists
+    d3::Buf list_p, cnt_p, list_c, cnt_c;
+    int cap_p = 0, cap_c = 0;
+    // per-atom results
+    d3::Buf cn, cnf, w, wd, P, Pf, G, Fp, U, vpart, vpart2;
+    // status
+    d3::Buf status, maxcnt;
+    int* h_status = nullptr;
+    hipStream_t last_stream = nullptr;
+    d3::Surrogate* sur = nullptr;
+    // MD scratch
+    d3::Buf md_scratch;
+
+    std::vector<d3::Buf*> all_buffers()
+    {
+        return {&d_tab, &d_c6, &d_pc, &bin_of, &shift, &count, &fill, &bin_start,
+                &scan_tmp, &bin_s, &perm, &pos_s, &shift_s, &ref_s, &type_copy,
+                &img_tab, &list_p, &cnt_p, &list_c, &cnt_c, &cn, &cnf, &w, &wd, &P,
+                &Pf, &G, &Fp, &U, &vpart, &vpart2, &status, &maxcnt, &md_scratch};
+    }
+};
+
+namespace d3 {
+
+int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const double* cell,
+          const int32_t* pbc, hipStream_t s);
+int rebuild_grow(d3_ctx* c, const double* pos, hipStream_t s);
+int update_positions(d3_ctx* c, const double* pos, hipStream_t s);
+int coordination(d3_ctx* c, int mode, hipStream_t s);
+int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial,
+             double* atom_energy, int acc, hipStream_t s);
+int read_status(d3_ctx* c, hipStream_t s, int* out);
+int status_code(int bits);
+int alloc_proj(d3_ctx* c, int mode);
+
+// surrogate (mlp.hip)
+void surrogate_free(d3_ctx* c);
+int surrogate_pair(d3_ctx* c, const PairScal& sc, hipStream_t s);
+
+}  // namespace d3

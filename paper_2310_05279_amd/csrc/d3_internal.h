@@ -1,0 +1,101 @@
+// Internal declarations shared by the library's HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/d3.h"
+
+namespace d3 {
+
+constexpr int WAVE = 64;
+constexpr int MAXREF = D3_MAX_REF;
+constexpr int MAXELEM = D3_MAX_ELEM;
+constexpr int BLOCK = 256;          // 4 waves per workgroup
+constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
+
+// device status bits (OR-ed by kernels, read by d3_status)
+constexpr int ST_SPECIES = 1;
+constexpr int ST_CAPACITY = 2;
+constexpr int ST_STALE = 4;
+constexpr int ST_NONFINITE = 8;
+
+// Bin layout and periodic images of one build.
+struct Geo {
+    double H[9];     // lattice vectors as rows
+    double Hinv[9];  // s_k = sum_m r_m Hinv[m*3+k]
+    int pbc[3];
+    int nb[3];       // bins along each lattice vector
+    int reach[3];    // stencil reach in bins
+    int timg[3];     // max |t_k| of image translations
+    int img_bits;    // list entry = (j << img_bits) | image
+    int n_img;
+    int nbins;
+};
+
+// Per-element data used inside kernels (kept in global memory).
+struct ElemTab {
+    int n_elem;
+    int n_ref[MAXELEM];
+    double cn_ref[MAXELEM * MAXREF];
+    double rcov[MAXELEM];
+};
+
+// Scalars of the dispersion pass.
+struct PairScal {
+    double s6, s8;
+    double rp2, rc2;  // evaluation cutoffs squared (no skin)
+};
+
+// ---- launchers (cells.hip) --------------------------------------------
+void launch_bin(int n, const double* pos, const int32_t* type, int n_elem,
+                const Geo& g, int* bin_of, double4* shift, int* count,
+                int* status, hipStream_t s);
+void launch_scan(int nbins, const int* count, int* bin_start, int* tmp,
+                 hipStream_t s);
+void launch_scatter(int n, const int* bin_of, const int* bin_start, int* fill,
+                    int* perm, hipStream_t s);
+void launch_binsort(int nbins, const int* bin_start, int* perm, int* bin_s,
+                    hipStream_t s);
+void launch_gather_build(int n, const double* pos, const int32_t* type, int n_elem,
+                         const int* perm, const double4* shift,
+                         double4* pos_s, double4* shift_s, double4* ref_s,
+                         hipStream_t s);
+void launch_list(int n, const double4* pos_s, const int* bin_s,
+                 const int* bin_start, const Geo& g, const double4* img_tab,
+                 double rp2, double rc2, uint32_t* list_p, int* cnt_p,
+                 int cap_p, uint32_t* list_c, int* cnt_c, int cap_c,
+                 int count_only, int* maxcnt, int* status, hipStream_t s);
+void launch_update(int n, const double* pos, const int* perm,
+                   const double4* shift_s, const double4* ref_s,
+                   double4* pos_s, double half_skin2, int* status,
+                   hipStream_t s);
+
+// ---- launchers (pair.hip) ---------------------------------------------
+int pass_waves(int n);
+void launch_cn(int mode, int n, const double4* pos_s, const double4* img_tab,
+               int img_bits, const uint32_t* list_c, const int* cnt_c,
+               int cap_c, const ElemTab* tab, const double* c6ref,
+               double rc2, double* cn, double* w, double* wd, double* P,
+               float* Pf, float* cnf, hipStream_t s);
+void launch_pair(int mode, int n, const double4* pos_s,
+                 const double4* img_tab, int img_bits,
+                 const uint32_t* list_p, const int* cnt_p, int cap_p,
+                 const ElemTab* tab, const double4* pc, PairScal sc,
+                 const double* w, const double* wd, const double* P,
+                 const float* Pf, double* Fp, double* U, double* G,
+                 double* vpart, hipStream_t s);
+void launch_chain(int mode, int n, const double4* pos_s,
+                  const double4* img_tab, int img_bits,
+                  const uint32_t* list_c, const int* cnt_c, int cap_c,
+                  const ElemTab* tab, double rc2, const double* G,
+                  const double* Fp, const double* U, const int* perm,
+                  double* forces, double* atom_energy, int accumulate,
+                  double* vpart, hipStream_t s);
+void launch_reduce(int n, const double* U, int nparts, const double* vpart,
+                   const double* vpart2, double* energy, double* virial,
+                   int accumulate, hipStream_t s);
+void launch_scatter_out(int n, const double* src, const int* perm,
+                        double* dst, hipStream_t s);
+
+}  // namespace d3

@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, it
+exports every function include/d3.h declares, and argument validation
+returns the documented error codes before any device work."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2310_05279_amd import d3
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "d3.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(d3_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_binding_surface():
+    assert set(_declared()) == set(d3.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(d3.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _create(**kw):
+    p = d3.make_params(**kw)
+    t = d3._Table(synth.make_table())
+    out = ctypes.c_void_p()
+    rc = d3.lib().d3_create(ctypes.byref(p), ctypes.byref(t.c), ctypes.byref(out))
+    return rc, out
+
+
+@pytest.mark.parametrize("kw", [dict(r_pot=-1.0), dict(r_cn=0.0), dict(skin=-0.1),
+                                dict(r_pot=float("nan")), dict(mode=7),
+                                dict(a1=float("inf"))])
+def test_create_rejects_bad_params(kw):
+    rc, out = _create(**kw)
+    assert rc == d3.D3_ERR_INVALID_ARG
+    assert out.value is None
+    assert d3.lib().d3_last_error()
+
+
+def test_create_rejects_bad_tables():
+    L = d3.lib()
+    p = d3.make_params()
+    out = ctypes.c_void_p()
+    for mutate in ("n_elem", "n_ref", "asym", "nan"):
+        tab = synth.make_table()
+        if mutate == "n_ref":
+            tab["n_ref"] = tab["n_ref"].copy()
+            tab["n_ref"][2] = 6
+        if mutate == "asym":
+            tab["c6_ref"] = tab["c6_ref"].copy()
+            tab["c6_ref"][0, 1, 0, 0] += 1.0
+        if mutate == "nan":
+            tab["rcov"] = tab["rcov"].copy()
+            tab["rcov"][1] = np.nan
+        t = d3._Table(tab)
+        if mutate == "n_elem":
+            t.c.n_elem = 17
+        assert L.d3_create(ctypes.byref(p), ctypes.byref(t.c), ctypes.byref(out)) == \
+            d3.D3_ERR_INVALID_ARG, mutate
+    assert L.d3_create(None, None, ctypes.byref(out)) == d3.D3_ERR_INVALID_ARG
+    assert L.d3_create(ctypes.byref(p), None, None) == d3.D3_ERR_INVALID_ARG
+
+
+def test_null_context_is_rejected_everywhere():
+    L = d3.lib()
+    assert L.d3_build_neighbors(None, 0, None, None, None, None, None) == d3.D3_ERR_INVALID_ARG
+    assert L.d3_coordination(None, None, None, None) == d3.D3_ERR_INVALID_ARG
+    assert L.d3_energy_forces_virial(None, None, None, None, None, None, 0, None) == \
+        d3.D3_ERR_INVALID_ARG
+    assert L.d3_status(None) == d3.D3_ERR_INVALID_ARG
+    assert L.d3_set_mode(None, 0) == d3.D3_ERR_INVALID_ARG
+    assert L.d3_list_stats(None, None) == d3.D3_ERR_INVALID_ARG
+    L.d3_destroy(None)  # accepted
+
+
+def test_error_message_is_per_call():
+    L = d3.lib()
+    L.d3_status(None)
+    assert b"NULL" in L.d3_last_error()

@@ -1,0 +1,290 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Plain FP64 gates: |dE|/atom <= 1e-6 eV, max |dF| <= 1e-5 eV/A; the virial
+is held to 1e-9 relative (it is FP64 throughout).  Precision form:
+max |dF| <= 1e-4 eV/A, errors of E and W reported.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import d3_oracle as O
+from oracle import d3_ref as R
+
+pytestmark = pytest.mark.gpu
+
+TAB = synth.make_table()
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    return torch
+
+
+def run_gpu(system, mode="plain", skin=0.0, table=TAB, prm=None, calc_out=False):
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    calc = d3.D3(table, mode=mode, skin=skin, **(prm or {}))
+    calc.build(system["pos"], system["types"], system["cell"], system["pbc"])
+    out = calc.compute()
+    cn = calc.coordination()
+    torch.cuda.synchronize()
+    calc.status()
+    res = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    res["energy"] = float(res["energy"][0])
+    res["cn"] = cn.cpu().numpy()
+    res["stats"] = calc.stats()
+    if calc_out:
+        return res, calc
+    calc.close()
+    return res
+
+
+def compare(gpu, ref, n, tol_e=1e-6, tol_f=1e-5, tol_w_rel=1e-9, label=""):
+    de = abs(gpu["energy"] - ref["energy"]) / max(n, 1)
+    df = np.abs(gpu["forces"] - ref["forces"]).max() if n else 0.0
+    wscale = max(np.abs(ref["virial"]).max(), 1e-30)
+    dw = np.abs(gpu["virial"] - ref["virial"]).max()
+    dae = np.abs(gpu["atom_energy"] - ref["atom_energy"]).max() if n else 0.0
+    dcn = np.abs(gpu["cn"] - ref["cn"]).max() if n else 0.0
+    print("%s |dE|/atom=%.2e max|dF|=%.2e max|dW|=%.2e (rel %.2e) max|dU_i|=%.2e max|dCN|=%.2e"
+          % (label, de, df, dw, dw / wscale, dae, dcn), flush=True)
+    assert de <= tol_e
+    assert df <= tol_f
+    assert dw <= tol_w_rel * wscale + 1e-14
+    assert dae <= tol_e
+    return de, df, dw
+
+
+def test_bilayer_graphene_144_plain():
+    """6x6 AB bilayer (144 atoms): several images of each atom within R_pot."""
+    g = synth.bilayer_graphene()
+    ref = O.d3(g["pos"], g["types"], g["cell"], g["pbc"], TAB)
+    gpu = run_gpu(g)
+    compare(gpu, ref, 144, label="graphene144")
+    assert np.abs(gpu["cn"] - ref["cn"]).max() < 1e-12
+
+
+def test_mof_3000_plain():
+    """3000-atom MOF-like cube: many 64-entry tiles per atom, ragged tails."""
+    m = synth.mof_like(3000, seed=31)
+    ref = R.d3(m["pos"], m["types"], m["cell"], m["pbc"], TAB)
+    gpu = run_gpu(m)
+    compare(gpu, ref, 3000, label="mof3000")
+    assert np.abs(gpu["cn"] - ref["cn"]).max() < 1e-12
+    assert gpu["stats"]["max_pot"] > 64 * 4
+
+
+def test_tiny_triclinic_cell_many_images():
+    """Four atoms in a skewed cell far smaller than R_pot: every atom sees
+    hundreds of images of every atom, itself included."""
+    cell = np.array([[5.0, 0.0, 0.0], [2.0, 4.6, 0.0], [0.5, 0.7, 5.3]])
+    s = np.random.default_rng(2).uniform(0, 1, (4, 3))
+    sys_ = {"pos": s @ cell, "types": np.array([0, 1, 2, 4], np.int32), "cell": cell,
+            "pbc": np.array([1, 1, 1], np.int32)}
+    ref = O.d3(sys_["pos"], sys_["types"], cell, sys_["pbc"], TAB)
+    gpu = run_gpu(sys_)
+    compare(gpu, ref, 4, label="tiny")
+
+
+def test_mixed_open_and_periodic_axes_and_unwrapped_positions():
+    """Slab periodic in-plane, open along z, with atoms displaced by lattice
+    vectors (outside the cell) and atoms outside the cell along the open
+    axis: same result as the oracle."""
+    m = synth.mof_like(600, seed=8)
+    cell = m["cell"].copy()
+    pbc = np.array([1, 1, 0], np.int32)
+    pos = m["pos"].copy()
+    rng = np.random.default_rng(4)
+    pos += rng.integers(-2, 3, (600, 1)) * cell[0] + rng.integers(-1, 2, (600, 1)) * cell[1]
+    pos[:20, 2] += 3.0 * cell[2, 2] / 4.0  # some beyond the open face
+    sys_ = {"pos": pos, "types": m["types"], "cell": cell, "pbc": pbc}
+    ref = R.d3(pos, m["types"], cell, pbc, TAB)
+    gpu = run_gpu(sys_)
+    compare(gpu, ref, 600, label="slab")
+
+
+def test_finite_cluster_no_pbc():
+    c = synth.cluster(80, 7.0, seed=5)
+    cell = np.eye(3) * 14.0
+    sys_ = {"pos": c["pos"] + 7.0, "types": c["types"], "cell": cell,
+            "pbc": np.array([0, 0, 0], np.int32)}
+    ref = O.d3(sys_["pos"], c["types"], None, (0, 0, 0), TAB)
+    gpu = run_gpu(sys_)
+    compare(gpu, ref, 80, label="cluster")
+    # a finite cluster: the virial is sum_i r_i (x) F_i
+    assert np.abs(gpu["virial"] - sys_["pos"].T @ gpu["forces"]).max() < 1e-10
+
+
+def test_single_reference_table():
+    """K_e = 1 for every element (C6 constant): the chain term vanishes."""
+    tab1 = synth.make_table(force_k=1)
+    m = synth.mof_like(800, seed=12)
+    ref = R.d3(m["pos"], m["types"], m["cell"], m["pbc"], tab1)
+    gpu = run_gpu(m, table=tab1)
+    compare(gpu, ref, 800, label="k1")
+
+
+def test_mof_24000_plain_config2():
+    """The 24 000-atom MOF-like cell: full comparison with the C oracle."""
+    m = synth.mof_like(24000)
+    ref = R.d3(m["pos"], m["types"], m["cell"], m["pbc"], TAB)
+    gpu = run_gpu(m)
+    compare(gpu, ref, 24000, label="mof24k")
+    assert np.abs(gpu["cn"] - ref["cn"]).max() < 1e-12
+
+
+@pytest.mark.parametrize("case", ["graphene", "mof"])
+def test_precision_form(case):
+    """FP32 pair arithmetic with FP64 cutoffs, weights and accumulation."""
+    if case == "graphene":
+        s = synth.bilayer_graphene(12, 12, seed=3)
+        ref = R.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB)
+    else:
+        s = synth.mof_like(3000, seed=31)
+        ref = R.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB)
+    n = s["pos"].shape[0]
+    gpu = run_gpu(s, mode="prec")
+    de, df, dw = compare(gpu, ref, n, tol_e=1e-6, tol_f=1e-4, tol_w_rel=1e-5,
+                         label="prec-" + case)
+
+
+def test_deterministic_and_accumulate():
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    m = synth.mof_like(2000, seed=3)
+    calc = d3.D3(TAB)
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    a = calc.compute()
+    b = calc.compute()
+    torch.cuda.synchronize()
+    for k in ("energy", "forces", "virial", "atom_energy"):
+        assert torch.equal(a[k], b[k]), k
+    # rebuild from scratch: same bits
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    c = calc.compute()
+    torch.cuda.synchronize()
+    for k in ("energy", "forces", "virial", "atom_energy"):
+        assert torch.equal(a[k], c[k]), k
+    # D3_ACCUMULATE adds onto existing outputs (Eq. 9 style)
+    out = {k: v.clone() for k, v in a.items()}
+    calc.compute(out=out, flags=d3.D3_ACCUMULATE)
+    torch.cuda.synchronize()
+    for k in ("energy", "forces", "virial", "atom_energy"):
+        assert torch.allclose(out[k], 2 * a[k], rtol=1e-15, atol=0), k
+    calc.status()
+    calc.close()
+
+
+def test_skin_reuse_stale_and_auto_rebuild():
+    """Lists built with a 1 A skin stay exact while atoms move < 0.5 A;
+    a larger move is flagged; D3_AUTO_REBUILD rebuilds and is exact."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    m = synth.mof_like(1500, seed=21)
+    calc = d3.D3(TAB, skin=1.0)
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    rng = np.random.default_rng(0)
+    d = rng.normal(size=m["pos"].shape)
+    d *= (0.45 * rng.uniform(size=(len(d), 1))) / np.linalg.norm(d, axis=1, keepdims=True)
+    p1 = m["pos"] + d
+    out = calc.compute(pos=p1)
+    torch.cuda.synchronize()
+    calc.status()
+    ref = R.d3(p1, m["types"], m["cell"], m["pbc"], TAB)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    g["energy"] = float(g["energy"][0])
+    g["cn"] = ref["cn"]
+    compare(g, ref, 1500, label="skin-reuse")
+    p2 = p1.copy()
+    p2[7] += np.array([0.7, 0.0, 0.0])
+    calc.compute(pos=p2)
+    torch.cuda.synchronize()
+    with pytest.raises(d3.D3Error) as ei:
+        calc.status()
+    assert ei.value.code == d3.D3_ERR_STALE
+    out = calc.compute(pos=p2, flags=d3.D3_AUTO_REBUILD)
+    torch.cuda.synchronize()
+    calc.status()
+    ref = R.d3(p2, m["types"], m["cell"], m["pbc"], TAB)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    g["energy"] = float(g["energy"][0])
+    g["cn"] = ref["cn"]
+    compare(g, ref, 1500, label="auto-rebuild")
+    calc.close()
+
+
+def test_bad_species_reported_and_contained():
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    m = synth.mof_like(500, seed=2)
+    t = m["types"].copy()
+    t[10] = 9
+    calc = d3.D3(TAB)
+    calc.build(m["pos"], t, m["cell"], m["pbc"])
+    calc.compute()
+    torch.cuda.synchronize()
+    with pytest.raises(d3.D3Error) as ei:
+        calc.status()
+    assert ei.value.code == d3.D3_ERR_SPECIES
+    calc.close()
+
+
+def test_empty_and_single_atom():
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    calc = d3.D3(TAB)
+    calc.build(np.zeros((0, 3)), np.zeros(0, np.int32), np.eye(3) * 10, (1, 1, 1))
+    out = calc.compute()
+    torch.cuda.synchronize()
+    assert out["energy"].item() == 0.0 and torch.all(out["virial"] == 0)
+    one = {"pos": np.array([[1.0, 2.0, 3.0]]), "types": np.array([2], np.int32),
+           "cell": np.eye(3) * 4.0, "pbc": np.array([1, 1, 1], np.int32)}
+    ref = O.d3(one["pos"], one["types"], one["cell"], one["pbc"], TAB)
+    gpu = run_gpu(one)
+    compare(gpu, ref, 1, label="one-atom")
+    assert np.abs(gpu["forces"]).max() < 1e-14
+    calc.close()
+
+
+def test_state_errors():
+    _torch()
+    from paper_2310_05279_amd import d3
+    calc = d3.D3(TAB)
+    e = __import__("torch").zeros(1, dtype=__import__("torch").float64, device="cuda")
+    with pytest.raises(d3.D3Error) as ei:
+        d3.d3_energy_forces_virial(calc.ctx, None, e)
+    assert ei.value.code == d3.D3_ERR_STATE
+    with pytest.raises(d3.D3Error) as ei:
+        calc.build(np.zeros((2, 3)), np.zeros(2, np.int32), np.zeros((3, 3)), (1, 1, 1))
+    assert ei.value.code == d3.D3_ERR_CELL
+    calc.close()
+
+
+@pytest.mark.parametrize("case", ["mof1M", "graphene500k"])
+def test_full_size_sampled(case):
+    """Full-size cells (10^6-atom MOF-like cube, 500 000-atom bilayer) in the
+    plain path: sampled atoms' forces, site energies and CNs against the
+    oracle's per-atom neighbourhood evaluation, plus invariants of the
+    whole result (zero net force, symmetric virial)."""
+    if case == "mof1M":
+        s = synth.mof_like(1_000_000)
+    else:
+        s = synth.bilayer_graphene(250, 500, seed=500000)
+    n = s["pos"].shape[0]
+    print("case", case, n, flush=True)
+    gpu = run_gpu(s)
+    idx = np.random.default_rng(7).choice(n, 12, replace=False)
+    ref = O.sampled(s["pos"], s["types"], s["cell"], s["pbc"], TAB, idx)
+    df = np.abs(gpu["forces"][idx] - ref["forces"]).max()
+    du = np.abs(gpu["atom_energy"][idx] - ref["atom_energy"]).max()
+    dcn = np.abs(gpu["cn"][idx] - ref["cn"]).max()
+    print(case, "sampled max|dF|=%.2e max|dU|=%.2e max|dCN|=%.2e" % (df, du, dcn), flush=True)
+    assert df <= 1e-5 and du <= 1e-6 and dcn <= 1e-12
+    fsum = np.abs(gpu["forces"].sum(0)).max()
+    assert fsum <= 1e-9 * n * max(1.0, np.abs(gpu["forces"]).max())
+    W = gpu["virial"]
+    assert np.abs(W - W.T).max() <= 1e-12 * np.abs(W).max()
+    assert abs(gpu["atom_energy"].sum() - gpu["energy"]) <= 1e-9 * abs(gpu["energy"])
