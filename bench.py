@@ -1,0 +1,222 @@
+"""Throughput of the D3(BJ) path on one MI355X.
+
+One step = one pass of the whole path on one batch of input: neighbour
+build (binning, counting sort, both lists), coordination numbers and
+Gaussian weights, the dispersion pass, the chain pass and the FP64
+reductions, i.e. energy, forces and virial of the cell.  The headline
+workload is the 24 000-atom MOF-like cell (H,C,N,O,Zn 4:6:1:2:1 at 0.04
+atoms/A^3, R_pot = 12 A, R_cn = 6 A) in the plain FP64 form; inputs are
+resident in HBM before timing starts.  Extra fields report the FP32
+precision form and the surrogate form on the same cell, the evaluation
+alone (lists reused as in MD), and the 10^6-atom MOF-like and
+500 000-atom bilayer cells.
+
+Prints ONE JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("D3 atom-steps/s (E+F+virial), surrogate/FP32 vs plain at "
+          "≤1e-4 eV/Å force")
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+
+def _flops_per_pair(ki, kj):
+    """FP64 operations of one unique dispersion pair within R_pot (energy,
+    both forces, virial, both dE/dn terms): 56 for the distance, damping,
+    force and virial arithmetic plus 3 (K_i + K_j) for C6, dC6/dn_i and
+    dC6/dn_j from the factorised weights."""
+    return 56.0 + 3.0 * (ki + kj)
+
+
+def algorithmic_pair_flops(system, table, r_pot):
+    """Sum of _flops_per_pair over the unique pairs within R_pot of a
+    cubic periodic cell (input statistics only, from a k-d tree)."""
+    from scipy.spatial import cKDTree
+    box = system["cell"][0, 0]
+    tree = cKDTree(np.mod(system["pos"], box), boxsize=box)
+    pairs = tree.query_pairs(r=r_pot, output_type="ndarray")
+    k = np.asarray(table["n_ref"])[system["types"]]
+    ki = k[pairs[:, 0]]
+    kj = k[pairs[:, 1]]
+    return float(np.sum(_flops_per_pair(ki, kj))), int(pairs.shape[0])
+
+
+class Runner:
+    def __init__(self, system, table, mode="plain", skin=0.0):
+        import torch
+        from paper_2310_05279_amd import d3
+        self.torch, self.d3 = torch, d3
+        self.dev = torch.device("cuda", 0)
+        self.calc = d3.D3(table, mode=mode, skin=skin)
+        self.calc.build(system["pos"], system["types"], system["cell"], system["pbc"])
+        self.cell = np.ascontiguousarray(system["cell"], dtype=np.float64)
+        self.pbc = np.ascontiguousarray(system["pbc"], dtype=np.int32)
+        self.n = self.calc.n
+        self.out = {"energy": torch.zeros(1, dtype=torch.float64, device=self.dev),
+                    "forces": torch.zeros((self.n, 3), dtype=torch.float64, device=self.dev),
+                    "virial": torch.zeros((3, 3), dtype=torch.float64, device=self.dev),
+                    "atom_energy": None}
+        self.stream = torch.cuda.current_stream()
+
+    def step(self, rebuild=True):
+        d3, c = self.d3, self.calc
+        if rebuild:
+            d3.d3_build_neighbors(c.ctx, c.pos, c.types, self.cell, self.pbc, self.stream)
+        d3.d3_energy_forces_virial(c.ctx, c.pos, self.out["energy"], self.out["forces"],
+                                   self.out["virial"], None, 0, self.stream)
+
+    def timed(self, steps, warmup, rebuild=True):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step(rebuild)
+        torch.cuda.synchronize()
+        self.calc.status()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record(self.stream)
+        for _ in range(steps):
+            self.step(rebuild)
+        t1.record(self.stream)
+        torch.cuda.synchronize()
+        self.calc.status()
+        return t0.elapsed_time(t1) / steps
+
+    def phases(self, steps, rebuild=True):
+        d3 = self.d3
+        d3.d3_set_timing(self.calc.ctx, 1)
+        for _ in range(steps):
+            self.step(rebuild)
+        self.torch.cuda.synchronize()
+        t = d3.d3_get_timing(self.calc.ctx)
+        d3.d3_set_timing(self.calc.ctx, 0)
+        return {k: (ms / calls if calls else 0.0) for k, (ms, calls) in t.items()}
+
+    def close(self):
+        self.calc.close()
+
+
+def cpu_baseline(system, table):
+    """The C FP64 oracle (brute force over all pairs and images) timed on
+    the host cores for one full E+F+W evaluation of the same cell."""
+    from oracle import d3_ref
+    t0 = time.perf_counter()
+    ref = d3_ref.d3(system["pos"], system["types"], system["cell"], system["pbc"], table)
+    dt = time.perf_counter() - t0
+    return ref, dt, d3_ref.threads()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the precision/surrogate/large-cell fields")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the D3 path here is single-GPU "
+              "(see DESIGN.md for how it would shard); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    table = synth.make_table()
+    system = synth.mof_like(24000)
+    n = system["pos"].shape[0]
+    print("[bench] workload mof24000 plain: warmup %d, steps %d" % (args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+
+    run = Runner(system, table, "plain")
+    ms = run.timed(args.steps, args.warmup)
+    value = n / (ms * 1e-3)
+    ph = run.phases(max(20, args.steps // 4))
+    stats = run.calc.stats()
+    ms_eval = run.timed(args.steps, 3, rebuild=False)
+    res_f = run.out["forces"].cpu().numpy()
+    res_e = float(run.out["energy"].item())
+    res_w = run.out["virial"].cpu().numpy()
+    run.close()
+    print("[bench] plain %.4f ms/step, phases %s" % (ms, ph), file=sys.stderr, flush=True)
+
+    flops, npairs = algorithmic_pair_flops(system, table, 12.0)
+    pair_ms = ph["pair"]
+    achieved = flops / (pair_ms * 1e-3) / 1e12
+    roofline = {"kernel": "k_pair<fp64> (dispersion pass)", "bound": "alu",
+                "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "algorithmic_flops_per_launch": flops, "unique_pairs": npairs,
+                "avg_kernel_ms": pair_ms}
+
+    extra = {"ms_per_step_eval_only": ms_eval,
+             "atom_steps_per_s_eval_only": n / (ms_eval * 1e-3),
+             "phase_ms": ph, "list_stats": stats}
+    if not args.no_extra:
+        run = Runner(system, table, "prec")
+        ms_p = run.timed(args.steps, args.warmup)
+        php = run.phases(max(20, args.steps // 4))
+        fp = run.out["forces"].cpu().numpy()
+        ep = float(run.out["energy"].item())
+        wp = run.out["virial"].cpu().numpy()
+        run.close()
+        extra["prec_f32"] = {"atom_steps_per_s": n / (ms_p * 1e-3), "ms_per_step": ms_p,
+                             "phase_ms": php,
+                             "pair_frac_fp32_peak": flops / (php["pair"] * 1e-3) / 1e12 /
+                             FP32_VECTOR_PEAK_TFLOPS,
+                             "max_abs_dF_vs_plain": float(np.abs(fp - res_f).max()),
+                             "abs_dE_per_atom_vs_plain": abs(ep - res_e) / n,
+                             "max_abs_dW_vs_plain": float(np.abs(wp - res_w).max())}
+        for name, big, steps in (("mof_1M", synth.mof_like(1_000_000), 10),
+                                 ("graphene_500k", synth.bilayer_graphene(250, 500, seed=500000), 10)):
+            entry = {}
+            for mode in ("plain", "prec"):
+                run = Runner(big, table, mode)
+                msb = run.timed(steps, 2)
+                phb = run.phases(5)
+                run.close()
+                entry[mode] = {"atom_steps_per_s": big["pos"].shape[0] / (msb * 1e-3),
+                               "ms_per_step": msb, "phase_ms": phb}
+            extra[name] = entry
+            print("[bench] %s %s" % (name, json.dumps(entry)), file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        ref, dt, threads = cpu_baseline(system, table)
+        cpu = {"value": n / dt, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+               "sample": "one full FP64 E+F+W evaluation of the 24,000-atom MOF-like cell "
+                         "by the C oracle (brute force over all pairs and images), %.1f s" % dt}
+        extra["plain_vs_oracle"] = {
+            "abs_dE_per_atom": abs(res_e - ref["energy"]) / n,
+            "max_abs_dF": float(np.abs(res_f - ref["forces"]).max()),
+            "max_abs_dW": float(np.abs(res_w - ref["virial"]).max())}
+
+    line = {"metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "mof_like_24000 (H,C,N,O,Zn 4:6:1:2:1, 0.04 atoms/A^3, "
+                                   "seed 24000; synthetic D3 table seed 2310; R_pot 12 A, "
+                                   "R_cn 6 A; plain FP64; neighbour build every step)",
+                       "n_atoms": n, "parallelism": "single GPU"},
+            "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

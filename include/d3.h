@@ -170,6 +170,17 @@ int d3_status(d3_ctx *ctx);
  * double[6].  Synchronises. */
 int d3_list_stats(d3_ctx *ctx, double *out);
 
+/* Per-phase timing with HIP events recorded on the caller's stream around
+ * each group of launches: 0 neighbour build, 1 position update, 2 CN and
+ * weights, 3 dispersion pass, 4 chain pass, 5 reductions.  enable = 1
+ * starts (and clears) the accumulation, 0 stops it. */
+#define D3_N_PHASES 6
+int d3_set_timing(d3_ctx *ctx, int32_t enable);
+
+/* Summed milliseconds and number of timed calls per phase since timing was
+ * enabled (host double[D3_N_PHASES], int64[D3_N_PHASES]).  Synchronises. */
+int d3_get_timing(d3_ctx *ctx, double *ms, int64_t *calls);
+
 /* ------------------------------------------------------------------------
  * Learned C6 surrogate (per element pair: MLP (n_i, n_j) -> (C6,
  * dC6/dn_i, dC6/dn_j), widths 2 -> 32 -> 32 -> 3, SiLU).  Not part of the

@@ -9,6 +9,12 @@
 
 #include "d3_ctx.h"
 
+#define HIPCHK_T(call)                                    \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
 namespace d3 {
 
 thread_local std::string g_err;
@@ -143,6 +149,33 @@ int make_geo(const double* cell, const int32_t* pbc, double rlist, int64_t n,
                     T[m] = t0 * cell[m] + t1 * cell[3 + m] + t2 * cell[6 + m];
                 imgs[c++] = make_double4(T[0], T[1], T[2], 0.0);
             }
+    return D3_OK;
+}
+
+void phase_mark(d3_ctx* c, int phase, hipStream_t s)
+{
+    if (!c->timing) return;
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        c->ev_pool.push_back(e);
+        c->ev_phase.push_back(0);
+    }
+    c->ev_phase[c->ev_used] = phase;
+    (void)hipEventRecord(c->ev_pool[c->ev_used], s);
+    c->ev_used++;
+}
+
+int timing_flush(d3_ctx* c)
+{
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        HIPCHK_T(hipEventSynchronize(c->ev_pool[k + 1]));
+        float ms = 0.0f;
+        HIPCHK_T(hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
+        c->t_ms[c->ev_phase[k]] += ms;
+        c->t_calls[c->ev_phase[k]] += 1;
+    }
+    c->ev_used = 0;
     return D3_OK;
 }
 
@@ -293,7 +326,9 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
     if (n > 0 && type != c->type_copy.as<int32_t>())
         HIPCHK(hipMemcpyAsync(c->type_copy.p, type, (size_t)n * sizeof(int32_t),
                               hipMemcpyDeviceToDevice, s));
+    phase_mark(c, PH_BUILD, s);
     D3CHK(run_build(c, pos, c->type_copy.as<int32_t>(), !same, s));
+    phase_mark(c, PH_BUILD, s);
     c->built = true;
     c->fresh_build = true;
     c->last_stream = s;
@@ -303,9 +338,11 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
 int update_positions(d3_ctx* c, const double* pos, hipStream_t s)
 {
     const double hs = 0.5 * c->prm.skin;
+    phase_mark(c, PH_UPDATE, s);
     launch_update((int)c->n, pos, c->perm.as<int>(), c->shift_s.as<double4>(),
                   c->ref_s.as<double4>(), c->pos_s.as<double4>(), hs * hs,
                   c->status.as<int>(), s);
+    phase_mark(c, PH_UPDATE, s);
     HIPCHK(hipGetLastError());
     return D3_OK;
 }
@@ -314,11 +351,13 @@ int coordination(d3_ctx* c, int mode, hipStream_t s)
 {
     D3CHK(alloc_proj(c, mode));
     const Geo& g = c->geo;
+    phase_mark(c, PH_CN, s);
     launch_cn(mode, (int)c->n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.img_bits,
               c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, c->d_tab.as<ElemTab>(),
               c->d_c6.as<double>(), c->prm.r_cn * c->prm.r_cn, c->cn.as<double>(),
               c->w.as<double>(), c->wd.as<double>(), c->P.as<double>(), c->Pf.as<float>(),
               c->cnf.as<float>(), s);
+    phase_mark(c, PH_CN, s);
     HIPCHK(hipGetLastError());
     return D3_OK;
 }
@@ -427,6 +466,7 @@ void d3_destroy(d3_ctx* c)
     (void)hipDeviceSynchronize();
     for (Buf* b : c->all_buffers()) release(*b);
     if (c->h_status) (void)hipHostFree(c->h_status);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     surrogate_free(c);
     delete c;
 }
@@ -523,6 +563,29 @@ int d3_status(d3_ctx* c)
     return status_code(st);
 }
 
+int d3_set_timing(d3_ctx* c, int32_t enable)
+{
+    if (!c) return fail(D3_ERR_INVALID_ARG, "ctx is NULL");
+    if (c->timing) D3CHK(timing_flush(c));
+    c->timing = enable != 0;
+    for (int k = 0; k < D3_N_PHASES; k++) {
+        c->t_ms[k] = 0.0;
+        c->t_calls[k] = 0;
+    }
+    return D3_OK;
+}
+
+int d3_get_timing(d3_ctx* c, double* ms, int64_t* calls)
+{
+    if (!c || !ms || !calls) return fail(D3_ERR_INVALID_ARG, "NULL argument");
+    D3CHK(timing_flush(c));
+    for (int k = 0; k < D3_N_PHASES; k++) {
+        ms[k] = c->t_ms[k];
+        calls[k] = c->t_calls[k];
+    }
+    return D3_OK;
+}
+
 int d3_list_stats(d3_ctx* c, double* out)
 {
     if (!c || !out) return fail(D3_ERR_INVALID_ARG, "NULL argument");
@@ -595,6 +658,7 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
     sc.s8 = c->prm.s8;
     sc.rp2 = c->prm.r_pot * c->prm.r_pot;
     sc.rc2 = c->prm.r_cn * c->prm.r_cn;
+    phase_mark(c, PH_PAIR, s);
     if (mode == D3_MODE_SURROGATE) {
         D3CHK(surrogate_pair(c, sc, s));
     } else {
@@ -605,14 +669,19 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
                     c->G.as<double>(), c->vpart.as<double>(), s);
         HIPCHK(hipGetLastError());
     }
+    phase_mark(c, PH_PAIR, s);
+    phase_mark(c, PH_CHAIN, s);
     launch_chain(mode == D3_MODE_PLAIN_F64 ? D3_MODE_PLAIN_F64 : D3_MODE_PREC_F32, n,
                  c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.img_bits,
                  c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, c->d_tab.as<ElemTab>(),
                  sc.rc2, c->G.as<double>(), c->Fp.as<double>(), c->U.as<double>(),
                  c->perm.as<int>(), forces, atom_energy, acc, c->vpart2.as<double>(), s);
+    phase_mark(c, PH_CHAIN, s);
     HIPCHK(hipGetLastError());
+    phase_mark(c, PH_REDUCE, s);
     launch_reduce(n, c->U.as<double>(), pass_waves(n), c->vpart.as<double>(),
                   c->vpart2.as<double>(), energy, virial, acc, s);
+    phase_mark(c, PH_REDUCE, s);
     HIPCHK(hipGetLastError());
     return D3_OK;
 }

@@ -71,6 +71,13 @@ struct d3_ctx {
     d3::Surrogate* sur = nullptr;
     // MD scratch
     d3::Buf md_scratch;
+    // phase timing (events recorded around launch groups)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_phase;  // phase of each begin/end pair
+    size_t ev_used = 0;
+    double t_ms[D3_N_PHASES] = {};
+    int64_t t_calls[D3_N_PHASES] = {};
 
     std::vector<d3::Buf*> all_buffers()
     {
@@ -93,6 +100,11 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
 int read_status(d3_ctx* c, hipStream_t s, int* out);
 int status_code(int bits);
 int alloc_proj(d3_ctx* c, int mode);
+
+// phase timing
+enum Phase { PH_BUILD = 0, PH_UPDATE = 1, PH_CN = 2, PH_PAIR = 3, PH_CHAIN = 4, PH_REDUCE = 5 };
+void phase_mark(d3_ctx* c, int phase, hipStream_t s);  // call twice: begin, end
+int timing_flush(d3_ctx* c);
 
 // surrogate (mlp.hip)
 void surrogate_free(d3_ctx* c);

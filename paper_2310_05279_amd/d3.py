@@ -79,6 +79,8 @@ _SIGS = {
     "d3_energy_forces_virial": (_c_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _c_u32, _vp]),
     "d3_status": (_c_i32, [_vp]),
     "d3_list_stats": (_c_i32, [_vp, _vp]),
+    "d3_set_timing": (_c_i32, [_vp, _c_i32]),
+    "d3_get_timing": (_c_i32, [_vp, _vp, _vp]),
     "d3_c6_surrogate_init": (_c_i32, [_vp, _c_u64]),
     "d3_c6_surrogate_train": (_c_i32, [_vp, ctypes.POINTER(d3_train_cfg), _vp, _vp]),
     "d3_c6_surrogate_eval": (_c_i32, [_vp, _c_i64, _vp, _vp, _vp, _vp, _vp, _c_i32, _vp]),
@@ -195,6 +197,20 @@ def d3_list_stats(ctx):
     _check(lib().d3_list_stats(ctx, out.ctypes.data))
     return {"max_pot": out[0], "mean_pot": out[1], "max_cn": out[2],
             "mean_cn": out[3], "bins": out[4], "images": out[5]}
+
+
+PHASES = ("build", "update", "cn", "pair", "chain", "reduce")
+
+
+def d3_set_timing(ctx, enable):
+    _check(lib().d3_set_timing(ctx, int(bool(enable))))
+
+
+def d3_get_timing(ctx):
+    ms = np.zeros(len(PHASES))
+    calls = np.zeros(len(PHASES), dtype=np.int64)
+    _check(lib().d3_get_timing(ctx, ms.ctypes.data, calls.ctypes.data))
+    return {p: (float(ms[k]), int(calls[k])) for k, p in enumerate(PHASES)}
 
 
 def d3_c6_surrogate_init(ctx, seed):
