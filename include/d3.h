@@ -172,7 +172,8 @@ int d3_list_stats(d3_ctx *ctx, double *out);
 
 /* Per-phase timing with HIP events recorded on the caller's stream around
  * each group of launches: 0 neighbour build, 1 position update, 2 CN and
- * weights, 3 dispersion pass, 4 chain pass, 5 reductions.  enable = 1
+ * weights, 3 dispersion pass, 4 chain pass with the final reductions,
+ * 5 unused (kept for layout).  enable = 1
  * starts (and clears) the accumulation, 0 stops it. */
 #define D3_N_PHASES 6
 int d3_set_timing(d3_ctx *ctx, int32_t enable);

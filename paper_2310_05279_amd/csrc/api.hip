@@ -207,7 +207,7 @@ int alloc_atoms(d3_ctx* c, int64_t n)
     D3CHK(ensure(c->bin_of, N * sizeof(int)));
     D3CHK(ensure(c->shift, N * sizeof(double4)));
     D3CHK(ensure(c->perm, N * sizeof(int)));
-    D3CHK(ensure(c->bin_s, N * sizeof(int)));
+    D3CHK(ensure(c->perm_tmp, N * sizeof(int)));
     D3CHK(ensure(c->pos_s, N * sizeof(double4)));
     D3CHK(ensure(c->shift_s, N * sizeof(double4)));
     D3CHK(ensure(c->ref_s, N * sizeof(double4)));
@@ -222,48 +222,57 @@ int alloc_atoms(d3_ctx* c, int64_t n)
     D3CHK(ensure(c->cnt_p, N * sizeof(int)));
     D3CHK(ensure(c->cnt_c, N * sizeof(int)));
     const size_t nw = (size_t)pass_waves((int)n);
-    D3CHK(ensure(c->vpart, nw * 6 * sizeof(double)));
-    D3CHK(ensure(c->vpart2, nw * 6 * sizeof(double)));
+    D3CHK(ensure(c->vpart, (nw / WAVES_PER_BLOCK) * 8 * sizeof(double)));
+    D3CHK(ensure(c->vpart2, (nw / WAVES_PER_BLOCK) * 8 * sizeof(double)));
     return D3_OK;
 }
 
 int alloc_proj(d3_ctx* c, int mode)
 {
     const size_t N = (size_t)(c->n > 0 ? c->n : 1);
-    const size_t m = (size_t)c->n_elem * N * MAXREF;
-    if (mode == D3_MODE_PREC_F32) return ensure(c->Pf, m * sizeof(float));
-    return ensure(c->P, m * sizeof(double));
+    // per-atom weight rows: 6 doubles (plain) or 8 floats (precision form)
+    if (mode == D3_MODE_PREC_F32) return ensure(c->Pf, N * 8 * sizeof(float));
+    return ensure(c->P, N * 6 * sizeof(double));
 }
 
 // Binning, counting sort and list construction on stream s.
+int list_stats(d3_ctx* c, hipStream_t s, int* mc)
+{
+    HIPCHK(hipMemsetAsync(c->maxcnt.p, 0, 8 * sizeof(int), s));
+    launch_cnt_stats((int)c->n, c->cnt_p.as<int>(), c->cnt_c.as<int>(), c->maxcnt.as<int>(), s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(mc, c->maxcnt.p, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return D3_OK;
+}
+
+// Binning, counting sort and list construction on stream s.  With
+// size_lists the list lengths are counted first and the capacities set
+// (one synchronisation).
 int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists,
               hipStream_t s)
 {
     const int n = (int)c->n;
     const Geo& g = c->geo;
-    HIPCHK(hipMemsetAsync(c->count.p, 0, (size_t)g.nbins * sizeof(int), s));
-    HIPCHK(hipMemsetAsync(c->fill.p, 0, (size_t)g.nbins * sizeof(int), s));
-    launch_bin(n, pos, type, c->n_elem, g, c->bin_of.as<int>(), c->shift.as<double4>(),
-               c->count.as<int>(), c->status.as<int>(), s);
-    launch_scan(g.nbins, c->count.as<int>(), c->bin_start.as<int>(), c->scan_tmp.as<int>(), s);
-    launch_scatter(n, c->bin_of.as<int>(), c->bin_start.as<int>(), c->fill.as<int>(),
-                   c->perm.as<int>(), s);
-    launch_binsort(g.nbins, c->bin_start.as<int>(), c->perm.as<int>(), c->bin_s.as<int>(), s);
-    launch_gather_build(n, pos, type, c->n_elem, c->perm.as<int>(), c->shift.as<double4>(),
-                        c->pos_s.as<double4>(), c->shift_s.as<double4>(),
-                        c->ref_s.as<double4>(), s);
+    int* count = c->count.as<int>();
+    int* fill = count + g.nbins;
+    HIPCHK(hipMemsetAsync(count, 0, 2 * (size_t)g.nbins * sizeof(int), s));
+    launch_bin(n, pos, type, c->n_elem, g, c->bin_of.as<int>(), c->shift.as<double4>(), count,
+               c->type_copy.as<int32_t>(), c->status.as<int>(), s);
+    launch_scan(g.nbins, count, c->bin_start.as<int>(), c->scan_tmp.as<int>(), s);
+    launch_scatter(n, c->bin_of.as<int>(), c->bin_start.as<int>(), fill, c->perm_tmp.as<int>(), s);
+    launch_rank(n, c->perm_tmp.as<int>(), c->bin_of.as<int>(), c->bin_start.as<int>(), pos,
+                c->type_copy.as<int32_t>(), c->shift.as<double4>(), c->perm.as<int>(),
+                c->pos_s.as<double4>(), c->shift_s.as<double4>(), c->ref_s.as<double4>(), s);
     HIPCHK(hipGetLastError());
     const double rp = c->prm.r_pot + c->prm.skin, rcn = c->prm.r_cn + c->prm.skin;
     if (size_lists) {
-        HIPCHK(hipMemsetAsync(c->maxcnt.p, 0, 8 * sizeof(int), s));
-        launch_list(n, c->pos_s.as<double4>(), c->bin_s.as<int>(), c->bin_start.as<int>(), g,
-                    c->img_tab.as<double4>(), rp * rp, rcn * rcn, nullptr, c->cnt_p.as<int>(), 0,
-                    nullptr, c->cnt_c.as<int>(), 0, 1, c->maxcnt.as<int>(),
-                    c->status.as<int>(), s);
+        launch_list(n, c->pos_s.as<double4>(), c->bin_start.as<int>(), g, c->img_tab.as<double4>(),
+                    rp * rp, rcn * rcn, nullptr, c->cnt_p.as<int>(), 0, nullptr,
+                    c->cnt_c.as<int>(), 0, 1, c->status.as<int>(), s);
         HIPCHK(hipGetLastError());
         int mc[8];
-        HIPCHK(hipMemcpyAsync(mc, c->maxcnt.p, sizeof(mc), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        D3CHK(list_stats(c, s, mc));
         // headroom for later rebuilds of the same geometry (MD)
         c->cap_p = std::max(1, mc[0] + std::max(16, mc[0] / 8));
         c->cap_c = std::max(1, mc[1] + std::max(16, mc[1] / 8));
@@ -273,11 +282,9 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
         D3CHK(ensure(c->list_p, N * c->cap_p * sizeof(uint32_t)));
         D3CHK(ensure(c->list_c, N * c->cap_c * sizeof(uint32_t)));
     }
-    HIPCHK(hipMemsetAsync(c->maxcnt.p, 0, 8 * sizeof(int), s));
-    launch_list(n, c->pos_s.as<double4>(), c->bin_s.as<int>(), c->bin_start.as<int>(), g,
-                c->img_tab.as<double4>(), rp * rp, rcn * rcn, c->list_p.as<uint32_t>(),
-                c->cnt_p.as<int>(), c->cap_p, c->list_c.as<uint32_t>(), c->cnt_c.as<int>(),
-                c->cap_c, 0, c->maxcnt.as<int>(), c->status.as<int>(), s);
+    launch_list(n, c->pos_s.as<double4>(), c->bin_start.as<int>(), g, c->img_tab.as<double4>(),
+                rp * rp, rcn * rcn, c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p,
+                c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, 0, c->status.as<int>(), s);
     HIPCHK(hipGetLastError());
     return D3_OK;
 }
@@ -313,8 +320,7 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
         c->geo = g;
         std::memcpy(c->cell, cell, sizeof(c->cell));
         D3CHK(alloc_atoms(c, n));
-        D3CHK(ensure(c->count, (size_t)g.nbins * sizeof(int)));
-        D3CHK(ensure(c->fill, (size_t)g.nbins * sizeof(int)));
+        D3CHK(ensure(c->count, 2 * (size_t)g.nbins * sizeof(int)));
         D3CHK(ensure(c->bin_start, ((size_t)g.nbins + 1) * sizeof(int)));
         D3CHK(ensure(c->scan_tmp, ((size_t)g.nbins / 1024 + 4) * sizeof(int)));
         D3CHK(ensure(c->img_tab, imgs.size() * sizeof(double4)));
@@ -323,11 +329,8 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
         HIPCHK(hipStreamSynchronize(s));
         c->built = false;
     }
-    if (n > 0 && type != c->type_copy.as<int32_t>())
-        HIPCHK(hipMemcpyAsync(c->type_copy.p, type, (size_t)n * sizeof(int32_t),
-                              hipMemcpyDeviceToDevice, s));
     phase_mark(c, PH_BUILD, s);
-    D3CHK(run_build(c, pos, c->type_copy.as<int32_t>(), !same, s));
+    D3CHK(run_build(c, pos, type, !same, s));
     phase_mark(c, PH_BUILD, s);
     c->built = true;
     c->fresh_build = true;
@@ -352,11 +355,10 @@ int coordination(d3_ctx* c, int mode, hipStream_t s)
     D3CHK(alloc_proj(c, mode));
     const Geo& g = c->geo;
     phase_mark(c, PH_CN, s);
-    launch_cn(mode, (int)c->n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.img_bits,
-              c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, c->d_tab.as<ElemTab>(),
-              c->d_c6.as<double>(), c->prm.r_cn * c->prm.r_cn, c->cn.as<double>(),
-              c->w.as<double>(), c->wd.as<double>(), c->P.as<double>(), c->Pf.as<float>(),
-              c->cnf.as<float>(), s);
+    launch_cn(mode, (int)c->n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img,
+              g.img_bits, c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c,
+              c->d_tab.as<ElemTab>(), c->prm.r_cn * c->prm.r_cn, c->cn.as<double>(),
+              c->w.as<double>(), c->wd.as<double>(), c->P.as<double>(), c->Pf.as<float>(), s);
     phase_mark(c, PH_CN, s);
     HIPCHK(hipGetLastError());
     return D3_OK;
@@ -430,7 +432,7 @@ int d3_create(const d3_params* prm, const d3_table* tab, d3_ctx** out)
             const double r0sq = 3.0 * tab->r2r4[e] * tab->r2r4[f] * BOHR_ANG * BOHR_ANG;
             const double rd = prm->a1 * std::sqrt(r0sq) + prm->a2;
             const double rd2 = rd * rd, rd6 = rd2 * rd2 * rd2;
-            pc[e * MAXELEM + f] = make_double4(rd6, rd6 * rd2, r0sq, 0.0);
+            pc[e * MAXELEM + f] = make_double4(rd6, rd6 * rd2, r0sq, prm->s8 * r0sq);
         }
     }
     c->h_c6 = c6;
@@ -440,7 +442,8 @@ int d3_create(const d3_params* prm, const d3_table* tab, d3_ctx** out)
     if ((r = ensure(c->d_tab, sizeof(ElemTab))) ||
         (r = ensure(c->d_c6, c6.size() * sizeof(double))) ||
         (r = ensure(c->d_pc, pc.size() * sizeof(double4))) ||
-        (r = ensure(c->status, 256)) || (r = ensure(c->maxcnt, 256))) {
+        (r = ensure(c->status, 256)) || (r = ensure(c->maxcnt, 256)) ||
+        (r = ensure(c->ticket, 256))) {
         d3_destroy(c);
         return r;
     }
@@ -448,6 +451,7 @@ int d3_create(const d3_params* prm, const d3_table* tab, d3_ctx** out)
     hipError_t e2 = hipMemcpy(c->d_c6.p, c6.data(), c6.size() * sizeof(double), hipMemcpyHostToDevice);
     hipError_t e3 = hipMemcpy(c->d_pc.p, pc.data(), pc.size() * sizeof(double4), hipMemcpyHostToDevice);
     hipError_t e4 = hipMemset(c->status.p, 0, 256);
+    if (e4 == hipSuccess) e4 = hipMemset(c->ticket.p, 0, 256);
     hipError_t e5 = hipHostMalloc((void**)&c->h_status, 64, hipHostMallocDefault);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess ||
         e5 != hipSuccess) {
@@ -591,8 +595,7 @@ int d3_list_stats(d3_ctx* c, double* out)
     if (!c || !out) return fail(D3_ERR_INVALID_ARG, "NULL argument");
     if (!c->built) return fail(D3_ERR_STATE, "no build yet");
     int mc[8];
-    HIPCHK(hipMemcpyAsync(mc, c->maxcnt.p, sizeof(mc), hipMemcpyDeviceToHost, c->last_stream));
-    HIPCHK(hipStreamSynchronize(c->last_stream));
+    D3CHK(list_stats(c, c->last_stream, mc));
     unsigned long long sp, sc;
     std::memcpy(&sp, &mc[2], 8);
     std::memcpy(&sc, &mc[4], 8);
@@ -623,8 +626,7 @@ int rebuild_grow(d3_ctx* c, const double* pos, hipStream_t s)
     D3CHK(read_status(c, s, &st));
     if (st & ST_CAPACITY) {
         int mc[8];
-        HIPCHK(hipMemcpyAsync(mc, c->maxcnt.p, sizeof(mc), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        D3CHK(list_stats(c, s, mc));
         c->cap_p = std::max(c->cap_p, mc[0] + std::max(16, mc[0] / 4));
         c->cap_c = std::max(c->cap_c, mc[1] + std::max(16, mc[1] / 4));
         c->cap_p = (c->cap_p + 3) & ~3;
@@ -662,26 +664,24 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
     if (mode == D3_MODE_SURROGATE) {
         D3CHK(surrogate_pair(c, sc, s));
     } else {
-        launch_pair(mode, n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.img_bits,
-                    c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p, c->d_tab.as<ElemTab>(),
-                    c->d_pc.as<double4>(), sc, c->w.as<double>(), c->wd.as<double>(),
-                    c->P.as<double>(), c->Pf.as<float>(), c->Fp.as<double>(), c->U.as<double>(),
+        launch_pair(mode, n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img,
+                    g.img_bits, c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p,
+                    c->d_tab.as<ElemTab>(), c->d_c6.as<double>(), c->d_pc.as<double4>(), sc,
+                    c->w.as<double>(), c->wd.as<double>(), c->P.as<double>(), c->Pf.as<float>(),
+                    c->Fp.as<double>(), c->U.as<double>(),
                     c->G.as<double>(), c->vpart.as<double>(), s);
         HIPCHK(hipGetLastError());
     }
     phase_mark(c, PH_PAIR, s);
     phase_mark(c, PH_CHAIN, s);
     launch_chain(mode == D3_MODE_PLAIN_F64 ? D3_MODE_PLAIN_F64 : D3_MODE_PREC_F32, n,
-                 c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.img_bits,
+                 c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img, g.img_bits,
                  c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, c->d_tab.as<ElemTab>(),
                  sc.rc2, c->G.as<double>(), c->Fp.as<double>(), c->U.as<double>(),
                  c->perm.as<int>(), forces, atom_energy, acc, c->vpart2.as<double>(), s);
-    phase_mark(c, PH_CHAIN, s);
     HIPCHK(hipGetLastError());
-    phase_mark(c, PH_REDUCE, s);
-    launch_reduce(n, c->U.as<double>(), pass_waves(n), c->vpart.as<double>(),
-                  c->vpart2.as<double>(), energy, virial, acc, s);
-    phase_mark(c, PH_REDUCE, s);
+    launch_final(n, c->vpart.as<double>(), c->vpart2.as<double>(), energy, virial, acc, s);
+    phase_mark(c, PH_CHAIN, s);
     HIPCHK(hipGetLastError());
     return D3_OK;
 }

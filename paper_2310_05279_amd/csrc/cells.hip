@@ -3,12 +3,17 @@
 // each widened by the skin.
 //
 // Atoms are binned along the three lattice vectors (fractional
-// coordinates, wrapped on periodic axes), sorted by bin with a counting
-// sort, and stored cell-sorted as double4 (x, y, z, species bits).  A bin
-// index runs fastest along the first lattice vector, so one stencil row of
-// bins is one contiguous range of sorted atoms.  One wavefront builds the
-// lists of one atom: it walks the stencil rows, tests 64 candidates per
-// step, and compacts the hits with a ballot.
+// coordinates, wrapped on periodic axes) and stored cell-sorted as double4
+// (x, y, z, species bits) by a counting sort whose order inside a bin is
+// the atom index (so every later sum has a fixed order).  A bin index runs
+// fastest along the first lattice vector, so one stencil row of bins is one
+// contiguous range of sorted atoms.
+//
+// One workgroup builds the lists of all atoms of one bin.  The atoms of
+// the bin's stencil (its candidates) are staged once into LDS with their
+// image translation already added; each wave then tests one atom of the
+// bin against the staged candidates, 64 per step, and compacts the hits
+// with a ballot.  Stencils that do not fit in LDS are processed in tiles.
 #include "d3_internal.h"
 
 namespace d3 {
@@ -19,16 +24,22 @@ __device__ __forceinline__ int floordiv(int a, int b)
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 
+static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
+
 __global__ void __launch_bounds__(BLOCK)
 k_bin(int n, const double* __restrict__ pos, const int32_t* __restrict__ type,
       int n_elem, Geo g, int* __restrict__ bin_of, double4* __restrict__ shift,
-      int* __restrict__ count, int* __restrict__ status)
+      int* __restrict__ count, int32_t* __restrict__ type_copy, int* __restrict__ status)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double r[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
     int t = type[i];
-    if (t < 0 || t >= n_elem) atomicOr(status, ST_SPECIES);
+    if (t < 0 || t >= n_elem) {
+        atomicOr(status, ST_SPECIES);
+        t = 0;  // contained: no later table lookup leaves its table
+    }
+    type_copy[i] = t;
     double sh[3] = {0.0, 0.0, 0.0};
     int b[3];
     bool finite = true;
@@ -47,7 +58,8 @@ k_bin(int n, const double* __restrict__ pos, const int32_t* __restrict__ type,
             q = floor(s * g.nb[k]);
         }
         // clamp: atoms outside the cell along an open axis (or at the
-        // rounding edge of a periodic one) join the edge bins
+        // rounding edge of a periodic one) join the edge bins; bin
+        // distances only shrink, so the stencil still covers every pair
         b[k] = !(q >= 0.0) ? 0 : (q >= (double)(g.nb[k] - 1) ? g.nb[k] - 1 : (int)q);
     }
     if (!finite) atomicOr(status, ST_NONFINITE);
@@ -57,7 +69,45 @@ k_bin(int n, const double* __restrict__ pos, const int32_t* __restrict__ type,
     atomicAdd(&count[bin], 1);
 }
 
-// three-phase exclusive scan, 1024 elements per block
+// Block-wide exclusive scan of one int per thread (LDS Hillis-Steele).
+__device__ int block_excl_scan(int v, int* sh, int* total)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        int t = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const int incl = sh[threadIdx.x];
+    *total = sh[blockDim.x - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// exclusive scan of the bin counts; one workgroup of 1024 threads, each
+// owning a contiguous chunk of bins
+__global__ void __launch_bounds__(1024)
+k_scan_one(int m, const int* __restrict__ in, int* __restrict__ out)
+{
+    __shared__ int sh[1024];
+    const int per = (m + 1023) / 1024;
+    const int a = threadIdx.x * per;
+    const int b = min(a + per, m);
+    int sum = 0;
+    for (int k = a; k < b; k++) sum += in[k];
+    int total;
+    int ex = block_excl_scan(sum, sh, &total);
+    for (int k = a; k < b; k++) {
+        const int v = in[k];
+        out[k] = ex;
+        ex += v;
+    }
+    if (threadIdx.x == 0) out[m] = total;
+}
+
+// three-phase exclusive scan for large bin tables, 1024 bins per block
 constexpr int SCAN_PER_BLOCK = 1024;
 
 __global__ void __launch_bounds__(BLOCK)
@@ -72,21 +122,14 @@ k_scan_local(int m, const int* __restrict__ in, int* __restrict__ out,
         v[q] = (base + q < m) ? in[base + q] : 0;
         s += v[q];
     }
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < BLOCK; off <<= 1) {
-        int t = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
-        __syncthreads();
-        sh[threadIdx.x] += t;
-        __syncthreads();
-    }
-    int excl = sh[threadIdx.x] - s;
+    int total;
+    int excl = block_excl_scan(s, sh, &total);
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         if (base + q < m) out[base + q] = excl;
         excl += v[q];
     }
-    if (threadIdx.x == BLOCK - 1) blocksum[blockIdx.x] = sh[BLOCK - 1];
+    if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
 }
 
 __global__ void __launch_bounds__(1024)
@@ -97,18 +140,10 @@ k_scan_top(int nblocks, int* __restrict__ blocksum, int* __restrict__ total)
     for (int c = 0; c < nblocks; c += 1024) {
         int i = c + threadIdx.x;
         int v = (i < nblocks) ? blocksum[i] : 0;
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            int t = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (i < nblocks) blocksum[i] = carry + sh[threadIdx.x] - v;
-        int last = sh[1023];
-        __syncthreads();
-        carry += last;
+        int tot;
+        int ex = block_excl_scan(v, sh, &tot);
+        if (i < nblocks) blocksum[i] = carry + ex;
+        carry += tot;
     }
     if (threadIdx.x == 0) *total = carry;
 }
@@ -124,55 +159,39 @@ k_scan_add(int m, int* __restrict__ out, const int* __restrict__ blocksum,
 
 __global__ void __launch_bounds__(BLOCK)
 k_scatter(int n, const int* __restrict__ bin_of, const int* __restrict__ bin_start,
-          int* __restrict__ fill, int* __restrict__ perm)
+          int* __restrict__ fill, int* __restrict__ perm_tmp)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int b = bin_of[i];
     int slot = bin_start[b] + atomicAdd(&fill[b], 1);
-    perm[slot] = i;
+    perm_tmp[slot] = i;
 }
 
-// Atomics leave the order inside a bin arbitrary; sorting each (short)
-// bin by atom index makes the layout, and every sum over it, deterministic.
+// The scatter leaves the order inside a bin arbitrary.  Each slot computes
+// the rank of its atom index among the bin's atoms and writes the atom to
+// the sorted position, gathering its wrapped position and species.
 __global__ void __launch_bounds__(BLOCK)
-k_binsort(int nbins, const int* __restrict__ bin_start, int* __restrict__ perm,
-          int* __restrict__ bin_s)
-{
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbins) return;
-    int s = bin_start[b], e = bin_start[b + 1];
-    for (int k = s + 1; k < e; k++) {
-        int v = perm[k];
-        int q = k - 1;
-        while (q >= s && perm[q] > v) {
-            perm[q + 1] = perm[q];
-            q--;
-        }
-        perm[q + 1] = v;
-    }
-    for (int k = s; k < e; k++) bin_s[k] = b;
-}
-
-__global__ void __launch_bounds__(BLOCK)
-k_gather_build(int n, const double* __restrict__ pos, const int32_t* __restrict__ type,
-               int n_elem, const int* __restrict__ perm, const double4* __restrict__ shift,
-               double4* __restrict__ pos_s, double4* __restrict__ shift_s,
-               double4* __restrict__ ref_s)
+k_rank(int n, const int* __restrict__ perm_tmp, const int* __restrict__ bin_of,
+       const int* __restrict__ bin_start, const double* __restrict__ pos,
+       const int32_t* __restrict__ type_copy, const double4* __restrict__ shift,
+       int* __restrict__ perm, double4* __restrict__ pos_s, double4* __restrict__ shift_s,
+       double4* __restrict__ ref_s)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    int i = perm[k];
-    double4 sh = shift[i];
-    double x = pos[3 * i] + sh.x, y = pos[3 * i + 1] + sh.y, z = pos[3 * i + 2] + sh.z;
-    // an out-of-range species was flagged by k_bin; clamp it so that no
-    // later table lookup leaves its table
-    int t = type[i];
-    t = (t < 0 || t >= n_elem) ? 0 : t;
-    double tb = __hiloint2double(0, t);
-    pos_s[k] = make_double4(x, y, z, tb);
-    shift_s[k] = sh;
-    ref_s[k] = make_double4(x, y, z, 0.0);
+    const int v = perm_tmp[k];
+    const int b = bin_of[v];
+    const int s = bin_start[b], e = bin_start[b + 1];
+    int rank = 0;
+    for (int q = s; q < e; q++) rank += (perm_tmp[q] < v) ? 1 : 0;
+    const int o = s + rank;
+    const double4 sh = shift[v];
+    const double x = pos[3 * v] + sh.x, y = pos[3 * v + 1] + sh.y, z = pos[3 * v + 2] + sh.z;
+    perm[o] = v;
+    pos_s[o] = make_double4(x, y, z, __hiloint2double(0, type_copy[v]));
+    shift_s[o] = sh;
+    ref_s[o] = make_double4(x, y, z, 0.0);
 }
 
 // Per-evaluation copy of the caller's positions into the cell-sorted
@@ -196,107 +215,222 @@ k_update(int n, const double* __restrict__ pos, const int* __restrict__ perm,
     pos_s[k] = make_double4(x, y, z, p.w);
 }
 
+constexpr int LIST_TILE = 2048;   // staged candidates per LDS tile
+constexpr int LIST_MAXSEG = 1024; // stencil segments per batch
+
 __global__ void __launch_bounds__(BLOCK)
-k_list(int n, const double4* __restrict__ pos_s, const int* __restrict__ bin_s,
-       const int* __restrict__ bin_start, Geo g, const double4* __restrict__ img_tab,
-       double rp2, double rc2, uint32_t* __restrict__ list_p, int* __restrict__ cnt_p,
-       int cap_p, uint32_t* __restrict__ list_c, int* __restrict__ cnt_c, int cap_c,
-       int count_only, int* __restrict__ maxcnt, int* __restrict__ status)
+k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start, Geo g,
+       const double4* __restrict__ img_tab, double rp2, double rc2,
+       uint32_t* __restrict__ list_p, int* __restrict__ cnt_p, int cap_p,
+       uint32_t* __restrict__ list_c, int* __restrict__ cnt_c, int cap_c, int count_only,
+       int* __restrict__ status)
 {
+    __shared__ double4 cand[LIST_TILE];
+    __shared__ int seg_jb[LIST_MAXSEG], seg_img[LIST_MAXSEG], seg_off[LIST_MAXSEG + 1];
+    __shared__ int sh[BLOCK];
+
+    const int bin = blockIdx.x;
+    const int s = bin_start[bin], e = bin_start[bin + 1];
+    if (s == e) return;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
-    const int nwaves = (gridDim.x * blockDim.x) / WAVE;
+    const int wv = threadIdx.x / WAVE;
+    const int nb0 = g.nb[0], nb1 = g.nb[1], nb2 = g.nb[2];
+    const int b0 = bin % nb0, b1 = (bin / nb0) % nb1, b2 = bin / (nb0 * nb1);
     const double rmax2 = rp2 > rc2 ? rp2 : rc2;
-    const int nim1 = 2 * g.timg[1] + 1, nim2 = 2 * g.timg[2] + 1;
-    const unsigned long long lanemask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int i = wave; i < n; i += nwaves) {
-        const double4 pi = pos_s[i];
-        const int bin = bin_s[i];
-        const int b0 = bin % g.nb[0];
-        const int b1 = (bin / g.nb[0]) % g.nb[1];
-        const int b2 = bin / (g.nb[0] * g.nb[1]);
-        int np = 0, nc = 0;
-        uint32_t* lp = list_p + (size_t)i * cap_p;
-        uint32_t* lc = list_c + (size_t)i * cap_c;
-        for (int d2 = -g.reach[2]; d2 <= g.reach[2]; d2++) {
-            int u2 = b2 + d2, t2, w2;
-            if (g.pbc[2]) { t2 = floordiv(u2, g.nb[2]); w2 = u2 - t2 * g.nb[2]; }
-            else { if (u2 < 0 || u2 >= g.nb[2]) continue; t2 = 0; w2 = u2; }
-            for (int d1 = -g.reach[1]; d1 <= g.reach[1]; d1++) {
-                int u1 = b1 + d1, t1, w1;
-                if (g.pbc[1]) { t1 = floordiv(u1, g.nb[1]); w1 = u1 - t1 * g.nb[1]; }
-                else { if (u1 < 0 || u1 >= g.nb[1]) continue; t1 = 0; w1 = u1; }
-                const int row = (w2 * g.nb[1] + w1) * g.nb[0];
-                int ua = b0 - g.reach[0], ub = b0 + g.reach[0];
-                int ta0, ta1;
-                if (g.pbc[0]) { ta0 = floordiv(ua, g.nb[0]); ta1 = floordiv(ub, g.nb[0]); }
-                else { ua = ua < 0 ? 0 : ua; ub = ub >= g.nb[0] ? g.nb[0] - 1 : ub; ta0 = ta1 = 0; }
-                for (int t0 = ta0; t0 <= ta1; t0++) {
-                    int lo = (ua > t0 * g.nb[0] ? ua : t0 * g.nb[0]) - t0 * g.nb[0];
-                    int hi = (ub < t0 * g.nb[0] + g.nb[0] - 1 ? ub : t0 * g.nb[0] + g.nb[0] - 1) - t0 * g.nb[0];
-                    if (lo > hi) continue;
-                    const int jb = bin_start[row + lo], je = bin_start[row + hi + 1];
-                    const int img = ((t0 + g.timg[0]) * nim1 + (t1 + g.timg[1])) * nim2 + (t2 + g.timg[2]);
-                    const double4 T = img_tab[img];
-                    const bool self_img = (t0 == 0 && t1 == 0 && t2 == 0);
-                    for (int j0 = jb; j0 < je; j0 += WAVE) {
-                        const int j = j0 + lane;
-                        bool inp = false, inc = false;
-                        if (j < je) {
-                            const double4 pj = pos_s[j];
-                            const double dx = pj.x + T.x - pi.x;
-                            const double dy = pj.y + T.y - pi.y;
-                            const double dz = pj.z + T.z - pi.z;
-                            const double r2 = dx * dx + dy * dy + dz * dz;
-                            const bool ok = !(self_img && j == i) && r2 < rmax2;
-                            inp = ok && r2 < rp2;
-                            inc = ok && r2 < rc2;
-                        }
-                        const unsigned long long bp = __ballot(inp);
-                        const unsigned long long bc = __ballot(inc);
-                        if (!count_only) {
-                            const uint32_t code = ((uint32_t)j << g.img_bits) | (uint32_t)img;
-                            if (inp) {
-                                int slot = np + __popcll(bp & lanemask);
-                                if (slot < cap_p) lp[slot] = code;
-                            }
-                            if (inc) {
-                                int slot = nc + __popcll(bc & lanemask);
-                                if (slot < cap_c) lc[slot] = code;
-                            }
-                        }
-                        np += __popcll(bp);
-                        nc += __popcll(bc);
+    const int n1 = 2 * g.timg[1] + 1, n2 = 2 * g.timg[2] + 1;
+    const int n1r = 2 * g.reach[1] + 1, n2r = 2 * g.reach[2] + 1;
+    const int nrows = n1r * n2r;
+    int ua = b0 - g.reach[0], ub = b0 + g.reach[0], ta0, ta1;
+    if (g.pbc[0]) {
+        ta0 = floordiv(ua, nb0);
+        ta1 = floordiv(ub, nb0);
+    } else {
+        ua = ua < 0 ? 0 : ua;
+        ub = ub >= nb0 ? nb0 - 1 : ub;
+        ta0 = ta1 = 0;
+    }
+    const int spr = ta1 - ta0 + 1;  // segments per row
+    int rpb = LIST_MAXSEG / spr;
+    rpb = rpb < 1 ? 1 : (rpb > BLOCK ? BLOCK : rpb);
+    const int img_self = (g.timg[0] * n1 + g.timg[1]) * n2 + g.timg[2];
+    const unsigned long long lanemask = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+    bool first = true;
+
+    for (int r0 = 0; r0 < nrows; r0 += rpb) {
+        const int rcount = (nrows - r0) < rpb ? (nrows - r0) : rpb;
+        if ((int)threadIdx.x < rcount) {
+            const int r = r0 + threadIdx.x;
+            const int u1 = b1 + (r % n1r - g.reach[1]);
+            const int u2 = b2 + (r / n1r - g.reach[2]);
+            int t1 = 0, w1 = u1, t2 = 0, w2 = u2;
+            bool ok = true;
+            if (g.pbc[1]) { t1 = floordiv(u1, nb1); w1 = u1 - t1 * nb1; }
+            else if (u1 < 0 || u1 >= nb1) ok = false;
+            if (g.pbc[2]) { t2 = floordiv(u2, nb2); w2 = u2 - t2 * nb2; }
+            else if (u2 < 0 || u2 >= nb2) ok = false;
+            for (int q = 0; q < spr; q++) {
+                const int slot = threadIdx.x * spr + q;
+                int len = 0, jb = 0, img = 0;
+                if (ok) {
+                    const int t0 = ta0 + q;
+                    const int lo = (ua > t0 * nb0 ? ua : t0 * nb0) - t0 * nb0;
+                    const int hi = (ub < t0 * nb0 + nb0 - 1 ? ub : t0 * nb0 + nb0 - 1) - t0 * nb0;
+                    if (lo <= hi) {
+                        const int row = (w2 * nb1 + w1) * nb0;
+                        jb = bin_start[row + lo];
+                        len = bin_start[row + hi + 1] - jb;
+                        img = ((t0 + g.timg[0]) * n1 + (t1 + g.timg[1])) * n2 + (t2 + g.timg[2]);
                     }
                 }
+                seg_jb[slot] = jb;
+                seg_img[slot] = img;
+                seg_off[slot] = len;
             }
         }
-        if (lane == 0) {
-            cnt_p[i] = np < cap_p ? np : cap_p;
-            cnt_c[i] = nc < cap_c ? nc : cap_c;
-            if (!count_only && (np > cap_p || nc > cap_c)) atomicOr(status, ST_CAPACITY);
-            atomicMax(&maxcnt[0], np);
-            atomicMax(&maxcnt[1], nc);
-            atomicAdd((unsigned long long*)&maxcnt[2], (unsigned long long)np);
-            atomicAdd((unsigned long long*)&maxcnt[4], (unsigned long long)nc);
+        __syncthreads();
+        const int nseg = rcount * spr;
+        const int base = threadIdx.x * 4;
+        int l[4], tsum = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            l[q] = (base + q < nseg) ? seg_off[base + q] : 0;
+            tsum += l[q];
+        }
+        int total;
+        int ex = block_excl_scan(tsum, sh, &total);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            if (base + q < nseg) seg_off[base + q] = ex;
+            ex += l[q];
+        }
+        __syncthreads();
+
+        for (int c0 = 0; c0 < total; c0 += LIST_TILE) {
+            const int tn = (total - c0) < LIST_TILE ? (total - c0) : LIST_TILE;
+            for (int t = threadIdx.x; t < tn; t += BLOCK) {
+                const int k = c0 + t;
+                int lo = 0, hi = nseg - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (seg_off[mid] <= k) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int j = seg_jb[lo] + (k - seg_off[lo]);
+                const int img = seg_img[lo];
+                const double4 p = pos_s[j];
+                const double4 T = img_tab[img];
+                const uint32_t code = ((uint32_t)j << g.img_bits) | (uint32_t)img;
+                cand[t] = make_double4(p.x + T.x, p.y + T.y, p.z + T.z,
+                                       __hiloint2double(0, (int)code));
+            }
+            __syncthreads();
+            for (int a = s + wv; a < e; a += WAVES_PER_BLOCK) {
+                const double4 pa = pos_s[a];
+                const uint32_t self_code = ((uint32_t)a << g.img_bits) | (uint32_t)img_self;
+                int np = first ? 0 : cnt_p[a];
+                int nc = first ? 0 : cnt_c[a];
+                uint32_t* lp = list_p + (size_t)a * cap_p;
+                uint32_t* lc = list_c + (size_t)a * cap_c;
+                for (int t0 = 0; t0 < tn; t0 += WAVE) {
+                    const int t = t0 + lane;
+                    bool inp = false, inc = false;
+                    uint32_t code = 0;
+                    if (t < tn) {
+                        const double4 q = cand[t];
+                        const double dx = q.x - pa.x, dy = q.y - pa.y, dz = q.z - pa.z;
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        code = (uint32_t)__double2loint(q.w);
+                        const bool ok = code != self_code && r2 < rmax2;
+                        inp = ok && r2 < rp2;
+                        inc = ok && r2 < rc2;
+                    }
+                    const unsigned long long bp = __ballot(inp);
+                    const unsigned long long bc = __ballot(inc);
+                    if (!count_only) {
+                        if (inp) {
+                            const int slot = np + __popcll(bp & lanemask);
+                            if (slot < cap_p) lp[slot] = code;
+                        }
+                        if (inc) {
+                            const int slot = nc + __popcll(bc & lanemask);
+                            if (slot < cap_c) lc[slot] = code;
+                        }
+                    }
+                    np += __popcll(bp);
+                    nc += __popcll(bc);
+                }
+                if (lane == 0) {
+                    cnt_p[a] = np;  // true count; readers clamp to the capacity
+                    cnt_c[a] = nc;
+                    if (!count_only && (np > cap_p || nc > cap_c)) atomicOr(status, ST_CAPACITY);
+                }
+            }
+            first = false;
+            __syncthreads();
+        }
+        if (total == 0 && first) {
+            // no candidate at all in this batch: counts still start at zero
+            for (int a = s + wv; a < e; a += WAVES_PER_BLOCK)
+                if (lane == 0) { cnt_p[a] = 0; cnt_c[a] = 0; }
+            first = false;
+            __syncthreads();
         }
     }
 }
 
-static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
+// max and sum of the list lengths (sizing and statistics)
+__global__ void __launch_bounds__(BLOCK)
+k_cnt_stats(int n, const int* __restrict__ cnt_p, const int* __restrict__ cnt_c,
+            int* __restrict__ out)
+{
+    __shared__ unsigned long long sh[4][BLOCK];
+    unsigned long long mp = 0, mc = 0, sp = 0, sc = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const unsigned long long a = (unsigned)cnt_p[i], b = (unsigned)cnt_c[i];
+        mp = a > mp ? a : mp;
+        mc = b > mc ? b : mc;
+        sp += a;
+        sc += b;
+    }
+    sh[0][threadIdx.x] = mp;
+    sh[1][threadIdx.x] = mc;
+    sh[2][threadIdx.x] = sp;
+    sh[3][threadIdx.x] = sc;
+    __syncthreads();
+    for (int off = BLOCK / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            const int o = threadIdx.x + off;
+            sh[0][threadIdx.x] = sh[0][o] > sh[0][threadIdx.x] ? sh[0][o] : sh[0][threadIdx.x];
+            sh[1][threadIdx.x] = sh[1][o] > sh[1][threadIdx.x] ? sh[1][o] : sh[1][threadIdx.x];
+            sh[2][threadIdx.x] += sh[2][o];
+            sh[3][threadIdx.x] += sh[3][o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(&out[0], (int)sh[0][0]);
+        atomicMax(&out[1], (int)sh[1][0]);
+        atomicAdd((unsigned long long*)&out[2], sh[2][0]);
+        atomicAdd((unsigned long long*)&out[4], sh[3][0]);
+    }
+}
 
 void launch_bin(int n, const double* pos, const int32_t* type, int n_elem,
                 const Geo& g, int* bin_of, double4* shift, int* count,
-                int* status, hipStream_t s)
+                int32_t* type_copy, int* status, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_bin, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s, n, pos,
-                       type, n_elem, g, bin_of, shift, count, status);
+                       type, n_elem, g, bin_of, shift, count, type_copy, status);
 }
 
 void launch_scan(int nbins, const int* count, int* bin_start, int* tmp,
                  hipStream_t s)
 {
+    if (nbins <= 1024 * 256) {
+        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, s, nbins, count, bin_start);
+        return;
+    }
     int nb = nblk(nbins, SCAN_PER_BLOCK);
     hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(BLOCK), 0, s, nbins, count,
                        bin_start, tmp);
@@ -306,28 +440,22 @@ void launch_scan(int nbins, const int* count, int* bin_start, int* tmp,
 }
 
 void launch_scatter(int n, const int* bin_of, const int* bin_start, int* fill,
-                    int* perm, hipStream_t s)
+                    int* perm_tmp, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_scatter, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s, n,
-                       bin_of, bin_start, fill, perm);
+                       bin_of, bin_start, fill, perm_tmp);
 }
 
-void launch_binsort(int nbins, const int* bin_start, int* perm, int* bin_s,
-                    hipStream_t s)
-{
-    hipLaunchKernelGGL(k_binsort, dim3(nblk(nbins, BLOCK)), dim3(BLOCK), 0, s,
-                       nbins, bin_start, perm, bin_s);
-}
-
-void launch_gather_build(int n, const double* pos, const int32_t* type, int n_elem,
-                         const int* perm, const double4* shift,
-                         double4* pos_s, double4* shift_s, double4* ref_s,
-                         hipStream_t s)
+void launch_rank(int n, const int* perm_tmp, const int* bin_of, const int* bin_start,
+                 const double* pos, const int32_t* type_copy, const double4* shift,
+                 int* perm, double4* pos_s, double4* shift_s, double4* ref_s,
+                 hipStream_t s)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_gather_build, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s,
-                       n, pos, type, n_elem, perm, shift, pos_s, shift_s, ref_s);
+    hipLaunchKernelGGL(k_rank, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s, n, perm_tmp,
+                       bin_of, bin_start, pos, type_copy, shift, perm, pos_s, shift_s,
+                       ref_s);
 }
 
 void launch_update(int n, const double* pos, const int* perm,
@@ -340,18 +468,23 @@ void launch_update(int n, const double* pos, const int* perm,
                        pos, perm, shift_s, ref_s, pos_s, half_skin2, status);
 }
 
-void launch_list(int n, const double4* pos_s, const int* bin_s,
-                 const int* bin_start, const Geo& g, const double4* img_tab,
-                 double rp2, double rc2, uint32_t* list_p, int* cnt_p,
-                 int cap_p, uint32_t* list_c, int* cnt_c, int cap_c,
-                 int count_only, int* maxcnt, int* status, hipStream_t s)
+void launch_list(int n, const double4* pos_s, const int* bin_start, const Geo& g,
+                 const double4* img_tab, double rp2, double rc2, uint32_t* list_p,
+                 int* cnt_p, int cap_p, uint32_t* list_c, int* cnt_c, int cap_c,
+                 int count_only, int* status, hipStream_t s)
 {
     if (n <= 0) return;
-    int waves = pass_waves(n);
-    hipLaunchKernelGGL(k_list, dim3(nblk(waves, WAVES_PER_BLOCK)), dim3(BLOCK), 0,
-                       s, n, pos_s, bin_s, bin_start, g, img_tab, rp2, rc2,
-                       list_p, cnt_p, cap_p, list_c, cnt_c, cap_c, count_only,
-                       maxcnt, status);
+    hipLaunchKernelGGL(k_list, dim3(g.nbins), dim3(BLOCK), 0, s, pos_s, bin_start, g,
+                       img_tab, rp2, rc2, list_p, cnt_p, cap_p, list_c, cnt_c, cap_c,
+                       count_only, status);
+}
+
+void launch_cnt_stats(int n, const int* cnt_p, const int* cnt_c, int* out, hipStream_t s)
+{
+    if (n <= 0) return;
+    int blocks = nblk(n, BLOCK);
+    blocks = blocks > 1024 ? 1024 : blocks;
+    hipLaunchKernelGGL(k_cnt_stats, dim3(blocks), dim3(BLOCK), 0, s, n, cnt_p, cnt_c, out);
 }
 
 }  // namespace d3

@@ -1,0 +1,204 @@
+// The chain pass through the coordination numbers (the many-body part of
+// Eqs. 5-7): per entry within R_cn, F_i += (G_i + G_j) f'(r) r_vec / r and
+// the matching virial, with f the counting function of Eq. 4 and
+// G = dE/dn from the dispersion pass; then the total force is written in
+// the caller's atom order.  The energy (Eq. 1) and virial totals are
+// summed afterwards from the workgroup partials of both passes in a fixed
+// order.
+#include "d3_device.h"
+
+namespace d3 {
+
+template <bool F32, bool IMG>
+__global__ void __launch_bounds__(BLOCK)
+k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_tab, int n_img,
+        int img_bits, const uint32_t* __restrict__ list_c, const int* __restrict__ cnt_c,
+        int cap_c, const ElemTab* __restrict__ tab, double rc2, const double* __restrict__ G,
+        const double* __restrict__ Fp, const double* __restrict__ U, const int* __restrict__ perm,
+        double* __restrict__ forces, double* __restrict__ atom_energy, int accumulate,
+        double* __restrict__ part)
+{
+    __shared__ double4 s_img[IMG ? IMG_LDS : 1];
+    __shared__ double s_rcov[MAXELEM];
+    load_images<IMG>(s_img, img_tab, n_img);
+    if (threadIdx.x < MAXELEM) s_rcov[threadIdx.x] = tab->rcov[threadIdx.x];
+    __syncthreads();
+    const int lane = threadIdx.x & (WAVE - 1);
+    const uint32_t img_mask = (1u << img_bits) - 1u;
+    double vir[6] = {0, 0, 0, 0, 0, 0};
+    const Walk wk = atom_walk(n);
+    for (int i = wk.first; i < wk.end; i += wk.step) {
+        const double4 pi = pos_s[i];
+        const int zi = __builtin_amdgcn_readfirstlane(zbits(pi.w));
+        const double rci = s_rcov[zi];
+        const double gi = G[i];
+        const int cnt = min(cnt_c[i], cap_c);
+        const uint32_t* lc = list_c + (size_t)i * cap_c;
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int k0 = 0; k0 < cnt; k0 += WAVE) {
+            const int k = k0 + lane;
+            const uint32_t code = list_code(lc, k, cnt, cap_c);
+            const uint32_t j = code >> img_bits;
+            const double4 pj = pos_s[j];
+            const double gj = G[j];
+            const double4 T = image<IMG>(s_img, img_tab, code & img_mask);
+            const double dx = pj.x + T.x - pi.x;
+            const double dy = pj.y + T.y - pi.y;
+            const double dz = pj.z + T.z - pi.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const bool in = k < cnt && r2 < rc2;
+            const double rs = rci + s_rcov[zbits(pj.w)];
+            const double gs = in ? gi + gj : 0.0;
+            if (F32) {
+                // masked lanes may see r = 0: keep their factor finite
+                const float q2 = in ? (float)r2 : 1.0f;
+                const float r = __fsqrt_rn(q2);
+                const float e = __expf(-16.0f * ((float)rs * __frcp_rn(r) - 1.0f));
+                const float ope = 1.0f + e;
+                // f'(r)/r = -16 Rs e / (r^3 (1+e)^2)
+                const float dfr = -16.0f * (float)rs * e * __frcp_rn(q2 * r * ope * ope);
+                const float coef = (float)gs * dfr;
+                const float x = (float)dx, y = (float)dy, zz = (float)dz;
+                fx += (double)(coef * x);
+                fy += (double)(coef * y);
+                fz += (double)(coef * zz);
+                const float h = -0.5f * coef;
+                const float hx = h * x, hy = h * y;
+                vir[0] += (double)(hx * x);
+                vir[1] += (double)(hx * y);
+                vir[2] += (double)(hx * zz);
+                vir[3] += (double)(hy * y);
+                vir[4] += (double)(hy * zz);
+                vir[5] += (double)(h * zz * zz);
+            } else {
+                const double q2 = in ? r2 : 1.0;
+                const double r = sqrt(q2);
+                const double e = exp(-16.0 * (rs / r - 1.0));
+                const double ope = 1.0 + e;
+                const double coef = gs * (-16.0 * rs * e / (q2 * r * ope * ope));
+                fx = fma(coef, dx, fx);
+                fy = fma(coef, dy, fy);
+                fz = fma(coef, dz, fz);
+                virial_add(vir, -0.5 * coef, dx, dy, dz);
+            }
+        }
+        fx = wave_sum(fx);
+        fy = wave_sum(fy);
+        fz = wave_sum(fz);
+        if (lane == 0) {
+            const size_t o = (size_t)perm[i];
+            const double f0 = Fp[3 * (size_t)i] + fx;
+            const double f1 = Fp[3 * (size_t)i + 1] + fy;
+            const double f2 = Fp[3 * (size_t)i + 2] + fz;
+            if (forces) {
+                if (accumulate) {
+                    forces[3 * o] += f0;
+                    forces[3 * o + 1] += f1;
+                    forces[3 * o + 2] += f2;
+                } else {
+                    forces[3 * o] = f0;
+                    forces[3 * o + 1] = f1;
+                    forces[3 * o + 2] = f2;
+                }
+            }
+            if (atom_energy) {
+                if (accumulate) atom_energy[o] += U[i];
+                else atom_energy[o] = U[i];
+            }
+        }
+    }
+    const double vals[7] = {0.0, vir[0], vir[1], vir[2], vir[3], vir[4], vir[5]};
+    block_partials(vals, part);
+}
+
+// Energy (Eq. 1) and virial from the workgroup partials of both passes,
+// summed in a fixed order by one workgroup.
+__global__ void __launch_bounds__(1024)
+k_final(int nparts, const double* __restrict__ part_a, const double* __restrict__ part_b,
+        double* __restrict__ energy, double* __restrict__ virial, int accumulate)
+{
+    __shared__ double fin[7][1024];
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nparts; b += 1024) {
+        const double4* pa = (const double4*)(part_a + (size_t)b * 8);
+        const double4* pb = (const double4*)(part_b + (size_t)b * 8);
+        const double4 a0 = pa[0], a1 = pa[1], c0 = pb[0], c1 = pb[1];
+        acc[0] += a0.x + c0.x;
+        acc[1] += a0.y + c0.y;
+        acc[2] += a0.z + c0.z;
+        acc[3] += a0.w + c0.w;
+        acc[4] += a1.x + c1.x;
+        acc[5] += a1.y + c1.y;
+        acc[6] += a1.z + c1.z;
+    }
+#pragma unroll
+    for (int c = 0; c < 7; c++) fin[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+#pragma unroll
+            for (int c = 0; c < 7; c++) fin[c][threadIdx.x] += fin[c][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double e = fin[0][0];
+        const double v[9] = {fin[1][0], fin[2][0], fin[3][0], fin[2][0], fin[4][0],
+                             fin[5][0], fin[3][0], fin[5][0], fin[6][0]};
+        if (accumulate) {
+            energy[0] += e;
+            if (virial)
+                for (int c = 0; c < 9; c++) virial[c] += v[c];
+        } else {
+            energy[0] = e;
+            if (virial)
+                for (int c = 0; c < 9; c++) virial[c] = v[c];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK)
+k_scatter_out(int n, const double* __restrict__ src, const int* __restrict__ perm,
+              double* __restrict__ dst)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[perm[k]] = src[k];
+}
+
+void launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
+                  int img_bits, const uint32_t* list_c, const int* cnt_c, int cap_c,
+                  const ElemTab* tab, double rc2, const double* G, const double* Fp,
+                  const double* U, const int* perm, double* forces, double* atom_energy,
+                  int accumulate, double* part, hipStream_t s)
+{
+    if (n <= 0) return;
+    const dim3 grid(split_blocks(n)), block(BLOCK);
+    const bool lds = n_img <= IMG_LDS;
+#define D3_CHAIN(F, I)                                                                          \
+    hipLaunchKernelGGL((k_chain<F, I>), grid, block, 0, s, n, pos_s, img_tab, n_img, img_bits,  \
+                       list_c, cnt_c, cap_c, tab, rc2, G, Fp, U, perm, forces, atom_energy,     \
+                       accumulate, part)
+    if (mode == D3_MODE_PREC_F32) {
+        if (lds) D3_CHAIN(true, true);
+        else D3_CHAIN(true, false);
+    } else {
+        if (lds) D3_CHAIN(false, true);
+        else D3_CHAIN(false, false);
+    }
+#undef D3_CHAIN
+}
+
+void launch_final(int n, const double* part_a, const double* part_b, double* energy,
+                  double* virial, int accumulate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, s, split_blocks(n), part_a, part_b,
+                       energy, virial, accumulate);
+}
+
+void launch_scatter_out(int n, const double* src, const int* perm, double* dst, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_scatter_out, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, n, src,
+                       perm, dst);
+}
+
+}  // namespace d3

@@ -57,7 +57,7 @@ struct d3_ctx {
     bool built = false;
     bool fresh_build = false;
     // cell-sorted data
-    d3::Buf bin_of, shift, count, fill, bin_start, scan_tmp, bin_s, perm;
+    d3::Buf bin_of, shift, count, bin_start, scan_tmp, perm_tmp, perm;
     d3::Buf pos_s, shift_s, ref_s, type_copy, img_tab;
     // lists
     d3::Buf list_p, cnt_p, list_c, cnt_c;
@@ -65,7 +65,7 @@ struct d3_ctx {
     // per-atom results
     d3::Buf cn, cnf, w, wd, P, Pf, G, Fp, U, vpart, vpart2;
     // status
-    d3::Buf status, maxcnt;
+    d3::Buf status, maxcnt, ticket;
     int* h_status = nullptr;
     hipStream_t last_stream = nullptr;
     d3::Surrogate* sur = nullptr;
@@ -81,10 +81,10 @@ struct d3_ctx {
 
     std::vector<d3::Buf*> all_buffers()
     {
-        return {&d_tab, &d_c6, &d_pc, &bin_of, &shift, &count, &fill, &bin_start,
-                &scan_tmp, &bin_s, &perm, &pos_s, &shift_s, &ref_s, &type_copy,
+        return {&d_tab, &d_c6, &d_pc, &bin_of, &shift, &count, &bin_start,
+                &scan_tmp, &perm_tmp, &perm, &pos_s, &shift_s, &ref_s, &type_copy,
                 &img_tab, &list_p, &cnt_p, &list_c, &cnt_c, &cn, &cnf, &w, &wd, &P,
-                &Pf, &G, &Fp, &U, &vpart, &vpart2, &status, &maxcnt, &md_scratch};
+                &Pf, &G, &Fp, &U, &vpart, &vpart2, &status, &maxcnt, &ticket, &md_scratch};
     }
 };
 

@@ -50,52 +50,52 @@ struct PairScal {
 // ---- launchers (cells.hip) --------------------------------------------
 void launch_bin(int n, const double* pos, const int32_t* type, int n_elem,
                 const Geo& g, int* bin_of, double4* shift, int* count,
-                int* status, hipStream_t s);
+                int32_t* type_copy, int* status, hipStream_t s);
 void launch_scan(int nbins, const int* count, int* bin_start, int* tmp,
                  hipStream_t s);
 void launch_scatter(int n, const int* bin_of, const int* bin_start, int* fill,
-                    int* perm, hipStream_t s);
-void launch_binsort(int nbins, const int* bin_start, int* perm, int* bin_s,
-                    hipStream_t s);
-void launch_gather_build(int n, const double* pos, const int32_t* type, int n_elem,
-                         const int* perm, const double4* shift,
-                         double4* pos_s, double4* shift_s, double4* ref_s,
-                         hipStream_t s);
-void launch_list(int n, const double4* pos_s, const int* bin_s,
-                 const int* bin_start, const Geo& g, const double4* img_tab,
-                 double rp2, double rc2, uint32_t* list_p, int* cnt_p,
-                 int cap_p, uint32_t* list_c, int* cnt_c, int cap_c,
-                 int count_only, int* maxcnt, int* status, hipStream_t s);
+                    int* perm_tmp, hipStream_t s);
+void launch_rank(int n, const int* perm_tmp, const int* bin_of, const int* bin_start,
+                 const double* pos, const int32_t* type_copy, const double4* shift,
+                 int* perm, double4* pos_s, double4* shift_s, double4* ref_s,
+                 hipStream_t s);
+void launch_list(int n, const double4* pos_s, const int* bin_start, const Geo& g,
+                 const double4* img_tab, double rp2, double rc2, uint32_t* list_p,
+                 int* cnt_p, int cap_p, uint32_t* list_c, int* cnt_c, int cap_c,
+                 int count_only, int* status, hipStream_t s);
+void launch_cnt_stats(int n, const int* cnt_p, const int* cnt_c, int* out, hipStream_t s);
 void launch_update(int n, const double* pos, const int* perm,
                    const double4* shift_s, const double4* ref_s,
                    double4* pos_s, double half_skin2, int* status,
                    hipStream_t s);
 
-// ---- launchers (pair.hip) ---------------------------------------------
-int pass_waves(int n);
-void launch_cn(int mode, int n, const double4* pos_s, const double4* img_tab,
-               int img_bits, const uint32_t* list_c, const int* cnt_c,
-               int cap_c, const ElemTab* tab, const double* c6ref,
-               double rc2, double* cn, double* w, double* wd, double* P,
-               float* Pf, float* cnf, hipStream_t s);
-void launch_pair(int mode, int n, const double4* pos_s,
-                 const double4* img_tab, int img_bits,
-                 const uint32_t* list_p, const int* cnt_p, int cap_p,
-                 const ElemTab* tab, const double4* pc, PairScal sc,
-                 const double* w, const double* wd, const double* P,
-                 const float* Pf, double* Fp, double* U, double* G,
-                 double* vpart, hipStream_t s);
-void launch_chain(int mode, int n, const double4* pos_s,
-                  const double4* img_tab, int img_bits,
-                  const uint32_t* list_c, const int* cnt_c, int cap_c,
-                  const ElemTab* tab, double rc2, const double* G,
-                  const double* Fp, const double* U, const int* perm,
-                  double* forces, double* atom_energy, int accumulate,
-                  double* vpart, hipStream_t s);
-void launch_reduce(int n, const double* U, int nparts, const double* vpart,
-                   const double* vpart2, double* energy, double* virial,
-                   int accumulate, hipStream_t s);
-void launch_scatter_out(int n, const double* src, const int* perm,
-                        double* dst, hipStream_t s);
+// ---- launchers (cn.hip, disp.hip, chain.hip) --------------------------
+// workgroups of the per-atom passes: up to 12 waves per SIMD, a whole
+// number of 8-workgroup groups (one group per XCD round)
+inline int split_blocks(int n)
+{
+    const int max_waves = 256 * 4 * 12;
+    if (n < 1) n = 1;
+    const int waves = n < max_waves ? n : max_waves;
+    return ((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK + 7) / 8 * 8;
+}
+inline int pass_waves(int n) { return split_blocks(n) * WAVES_PER_BLOCK; }
+void launch_cn(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
+               int img_bits, const uint32_t* list_c, const int* cnt_c, int cap_c,
+               const ElemTab* tab, double rc2, double* cn, double* w, double* wd, double* W,
+               float* Wf, hipStream_t s);
+void launch_pair(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
+                 int img_bits, const uint32_t* list_p, const int* cnt_p, int cap_p,
+                 const ElemTab* tab, const double* c6ref, const double4* pc, PairScal sc,
+                 const double* w, const double* wd, const double* W, const float* Wf, double* Fp,
+                 double* U, double* G, double* part, hipStream_t s);
+void launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
+                  int img_bits, const uint32_t* list_c, const int* cnt_c, int cap_c,
+                  const ElemTab* tab, double rc2, const double* G, const double* Fp,
+                  const double* U, const int* perm, double* forces, double* atom_energy,
+                  int accumulate, double* part, hipStream_t s);
+void launch_final(int n, const double* part_a, const double* part_b, double* energy,
+                  double* virial, int accumulate, hipStream_t s);
+void launch_scatter_out(int n, const double* src, const int* perm, double* dst, hipStream_t s);
 
 }  // namespace d3

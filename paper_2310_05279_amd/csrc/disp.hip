@@ -1,0 +1,249 @@
+// The BJ-damped dispersion pass (Eq. 2): per neighbour entry within R_pot,
+// C6 from Eq. 3, the direct force at fixed C6, the site energy U_i, the
+// derivative G_i = dE/dn_i and the virial.
+//
+// One wavefront treats one atom i at a time; its 64 lanes walk i's list,
+// 64 entries per step.  Every sum is a gather onto i (each unordered pair
+// is evaluated from both ends), so no floating-point atomics are used and
+// the results do not depend on scheduling.
+//
+// C6 factorises: the Gaussian weight of Eq. 3 is a product over the two
+// atoms and so is its normaliser, hence C6_ij = w_i^T M_{Zi Zj} w_j with
+// w the normalised per-atom weights.  When a wave takes atom i it forms in
+// LDS the row vectors u_f = w_i^T M_{Zi f} and u'_f = w_i'^T M_{Zi f} for
+// every element f, so a neighbour costs one 48-byte weight gather and
+// C6 = u_{Zj} . w_j, dC6/dn_i = u'_{Zj} . w_j.  The pair constants (Rd^6,
+// Rd^8, s8 R0^2) of every element pair sit in LDS too.  List codes are
+// fetched two chunks and neighbour data one chunk ahead of the arithmetic;
+// every lane loads a valid address (entries past the count read atom 0 and
+// are masked), so the loads carry no branches.
+//
+// Precision form (D3_MODE_PREC_F32): distances and cutoff tests in FP64,
+// then the pair arithmetic in FP32 (hardware rcp) on FP32 weights, with
+// every per-lane and per-atom sum accumulated in FP64.
+#include <type_traits>
+
+#include "d3_device.h"
+
+namespace d3 {
+
+constexpr int M_LDS_ELEM = 8;  // C6 reference table staged in LDS up to 8 elements
+
+template <bool F32>
+struct Nbr;
+template <>
+struct Nbr<false> {
+    double4 p;
+    double2 w01, w23;
+    double w4;
+};
+template <>
+struct Nbr<true> {
+    double4 p;
+    float4 w03;
+    float w4;
+};
+
+template <bool F32>
+__device__ __forceinline__ void fetch(Nbr<F32>& nb, uint32_t code, int img_bits,
+                                      const double4* __restrict__ pos_s,
+                                      const double* __restrict__ W, const float* __restrict__ Wf)
+{
+    const uint32_t j = code >> img_bits;
+    nb.p = pos_s[j];
+    if constexpr (F32) {
+        nb.w03 = *(const float4*)(Wf + (size_t)j * WROWF);
+        nb.w4 = Wf[(size_t)j * WROWF + 4];
+    } else {
+        const double2* r = (const double2*)(W + (size_t)j * WROW);
+        nb.w01 = r[0];
+        nb.w23 = r[1];
+        nb.w4 = W[(size_t)j * WROW + 4];
+    }
+}
+
+template <bool F32, bool IMG>
+__global__ void __launch_bounds__(BLOCK)
+k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_tab, int n_img,
+       int img_bits, const uint32_t* __restrict__ list_p, const int* __restrict__ cnt_p, int cap_p,
+       const ElemTab* __restrict__ tab, const double* __restrict__ c6ref,
+       const double4* __restrict__ pc, PairScal sc, const double* __restrict__ w,
+       const double* __restrict__ wd, const double* __restrict__ W, const float* __restrict__ Wf,
+       double* __restrict__ Fp, double* __restrict__ U, double* __restrict__ G,
+       double* __restrict__ part)
+{
+    typedef typename std::conditional<F32, float, double>::type real;
+    __shared__ double4 s_img[IMG ? IMG_LDS : 1];
+    __shared__ double4 s_pc[MAXELEM * MAXELEM];
+    __shared__ double s_M[M_LDS_ELEM * M_LDS_ELEM * MAXREF * MAXREF];
+    __shared__ real s_u[WAVES_PER_BLOCK][2][MAXELEM * MAXREF];
+    const int ne = tab->n_elem;
+    const bool m_lds = ne <= M_LDS_ELEM;
+    load_images<IMG>(s_img, img_tab, n_img);
+    for (int k = threadIdx.x; k < MAXELEM * MAXELEM; k += blockDim.x) s_pc[k] = pc[k];
+    if (m_lds)
+        for (int k = threadIdx.x; k < ne * ne * MAXREF * MAXREF; k += blockDim.x) {
+            const int e = k / (ne * MAXREF * MAXREF), r = k - e * ne * MAXREF * MAXREF;
+            s_M[k] = c6ref[(size_t)e * MAXELEM * MAXREF * MAXREF + r];
+        }
+    __syncthreads();
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const uint32_t img_mask = (1u << img_bits) - 1u;
+    real* u = &s_u[wv][0][0];
+    real* ud = &s_u[wv][1][0];
+    double vir[6] = {0, 0, 0, 0, 0, 0};
+    double esum = 0.0;
+    const Walk wk = atom_walk(n);
+    for (int i = wk.first; i < wk.end; i += wk.step) {
+        const double4 pi = pos_s[i];
+        const int zi = __builtin_amdgcn_readfirstlane(zbits(pi.w));
+        const int cnt = min(cnt_p[i], cap_p);
+        const uint32_t* lp = list_p + (size_t)i * cap_p;
+        // list codes of the first two chunks go out first
+        uint32_t code_c = list_code(lp, lane, cnt, cap_p);
+        uint32_t code_n = list_code(lp, WAVE + lane, cnt, cap_p);
+        // u_f = w_i^T M[zi][f] and u'_f = w_i'^T M[zi][f], this wave's LDS
+        double wi[MAXREF], wdi[MAXREF];
+#pragma unroll
+        for (int a = 0; a < MAXREF; a++) {
+            wi[a] = w[(size_t)i * MAXREF + a];
+            wdi[a] = wd[(size_t)i * MAXREF + a];
+        }
+        for (int idx = lane; idx < 2 * ne * MAXREF; idx += WAVE) {
+            const int which = idx >= ne * MAXREF ? 1 : 0;
+            const int q = idx - which * ne * MAXREF;
+            const int f = q / MAXREF, b = q - f * MAXREF;
+            double v = 0.0;
+#pragma unroll
+            for (int a = 0; a < MAXREF; a++) {
+                const double mab = m_lds ? s_M[((zi * ne + f) * MAXREF + a) * MAXREF + b]
+                                         : c6ref[((size_t)(zi * MAXELEM + f) * MAXREF + a) * MAXREF + b];
+                v = fma(which ? wdi[a] : wi[a], mab, v);
+            }
+            s_u[wv][which][q] = (real)v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        Nbr<F32> nb_c;
+        fetch<F32>(nb_c, code_c, img_bits, pos_s, W, Wf);
+        double fx = 0.0, fy = 0.0, fz = 0.0, ue = 0.0, g = 0.0;
+        for (int k0 = 0; k0 < cnt; k0 += WAVE) {
+            const int k = k0 + lane;
+            // prefetch: codes two chunks ahead, neighbour data one chunk ahead
+            const uint32_t code_nn = list_code(lp, k + 2 * WAVE, cnt, cap_p);
+            Nbr<F32> nb_n;
+            fetch<F32>(nb_n, code_n, img_bits, pos_s, W, Wf);
+            const double4 T = image<IMG>(s_img, img_tab, code_c & img_mask);
+            const double dx = nb_c.p.x + T.x - pi.x;
+            const double dy = nb_c.p.y + T.y - pi.y;
+            const double dz = nb_c.p.z + T.z - pi.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const bool in = k < cnt && r2 < sc.rp2;
+            const int zj = zbits(nb_c.p.w);
+            const real* uz = u + zj * MAXREF;
+            const real* udz = ud + zj * MAXREF;
+            const double4 c = s_pc[zi * MAXELEM + zj];  // Rd^6, Rd^8, R0^2, s8 R0^2
+            if constexpr (!F32) {
+                const double wj[MAXREF] = {nb_c.w01.x, nb_c.w01.y, nb_c.w23.x, nb_c.w23.y,
+                                           nb_c.w4};
+                double c6 = 0.0, dc6 = 0.0;
+#pragma unroll
+                for (int b = 0; b < MAXREF; b++) {
+                    c6 = fma(uz[b], wj[b], c6);
+                    dc6 = fma(udz[b], wj[b], dc6);
+                }
+                c6 = in ? c6 : 0.0;
+                dc6 = in ? dc6 : 0.0;
+                const double r4 = r2 * r2, r6 = r4 * r2, r8 = r4 * r4;
+                const double A = r6 + c.x, B = r8 + c.y;
+                const double inv = 1.0 / (A * B);
+                const double t6 = B * inv, t8 = A * inv;
+                const double a6 = sc.s6 * t6, a8 = c.w * t8;
+                const double gg = a6 + a8;  // -dphi/dC6
+                const double dphi_r = c6 * (6.0 * a6 * r4 * t6 + 8.0 * a8 * r6 * t8);
+                ue = fma(-0.5 * c6, gg, ue);
+                g = fma(-gg, dc6, g);
+                fx = fma(dphi_r, dx, fx);
+                fy = fma(dphi_r, dy, fy);
+                fz = fma(dphi_r, dz, fz);
+                virial_add(vir, -0.5 * dphi_r, dx, dy, dz);
+            } else {
+                const float wj[MAXREF] = {nb_c.w03.x, nb_c.w03.y, nb_c.w03.z, nb_c.w03.w, nb_c.w4};
+                float c6 = 0.0f, dc6 = 0.0f;
+#pragma unroll
+                for (int b = 0; b < MAXREF; b++) {
+                    c6 = fmaf(uz[b], wj[b], c6);
+                    dc6 = fmaf(udz[b], wj[b], dc6);
+                }
+                c6 = in ? c6 : 0.0f;
+                dc6 = in ? dc6 : 0.0f;
+                const float x = (float)dx, y = (float)dy, zz = (float)dz;
+                const float q2 = (float)r2;
+                const float r4 = q2 * q2, r6 = r4 * q2, r8 = r4 * r4;
+                const float t6 = __frcp_rn(r6 + (float)c.x), t8 = __frcp_rn(r8 + (float)c.y);
+                const float a6 = (float)sc.s6 * t6, a8 = (float)c.w * t8;
+                const float gg = a6 + a8;
+                const float dphi_r = c6 * (6.0f * a6 * r4 * t6 + 8.0f * a8 * r6 * t8);
+                ue += (double)(-0.5f * c6 * gg);
+                g += (double)(-gg * dc6);
+                fx += (double)(dphi_r * x);
+                fy += (double)(dphi_r * y);
+                fz += (double)(dphi_r * zz);
+                const float h = -0.5f * dphi_r;
+                const float hx = h * x, hy = h * y;
+                vir[0] += (double)(hx * x);
+                vir[1] += (double)(hx * y);
+                vir[2] += (double)(hx * zz);
+                vir[3] += (double)(hy * y);
+                vir[4] += (double)(hy * zz);
+                vir[5] += (double)(h * zz * zz);
+            }
+            code_c = code_n;
+            code_n = code_nn;
+            nb_c = nb_n;
+        }
+        fx = wave_sum(fx);
+        fy = wave_sum(fy);
+        fz = wave_sum(fz);
+        ue = wave_sum(ue);
+        g = wave_sum(g);
+        esum += ue;
+        if (lane == 0) {
+            Fp[3 * (size_t)i] = fx;
+            Fp[3 * (size_t)i + 1] = fy;
+            Fp[3 * (size_t)i + 2] = fz;
+            U[i] = ue;
+            G[i] = g;
+        }
+        // the next atom rewrites u: every lane has finished reading it
+        __builtin_amdgcn_wave_barrier();
+    }
+    // energy enters once per wave (esum is wave-uniform), virial per lane
+    const double vals[7] = {lane == 0 ? esum : 0.0, vir[0], vir[1], vir[2], vir[3], vir[4], vir[5]};
+    block_partials(vals, part);
+}
+
+void launch_pair(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
+                 int img_bits, const uint32_t* list_p, const int* cnt_p, int cap_p,
+                 const ElemTab* tab, const double* c6ref, const double4* pc, PairScal sc,
+                 const double* w, const double* wd, const double* W, const float* Wf, double* Fp,
+                 double* U, double* G, double* part, hipStream_t s)
+{
+    if (n <= 0) return;
+    const dim3 grid(split_blocks(n)), block(BLOCK);
+    const bool lds = n_img <= IMG_LDS;
+#define D3_PAIR(F, I)                                                                          \
+    hipLaunchKernelGGL((k_pair<F, I>), grid, block, 0, s, n, pos_s, img_tab, n_img, img_bits,  \
+                       list_p, cnt_p, cap_p, tab, c6ref, pc, sc, w, wd, W, Wf, Fp, U, G, part)
+    if (mode == D3_MODE_PREC_F32) {
+        if (lds) D3_PAIR(true, true);
+        else D3_PAIR(true, false);
+    } else {
+        if (lds) D3_PAIR(false, true);
+        else D3_PAIR(false, false);
+    }
+#undef D3_PAIR
+}
+
+}  // namespace d3
