@@ -215,9 +215,15 @@ k_update(int n, const double* __restrict__ pos, const int* __restrict__ perm,
     pos_s[k] = make_double4(x, y, z, p.w);
 }
 
-constexpr int LIST_TILE = 2048;   // staged candidates per LDS tile
-constexpr int LIST_MAXSEG = 1024; // stencil segments per batch
+constexpr int LIST_TILE = 2048;  // staged candidates per LDS tile
+constexpr int LIST_MAXSEG = 512; // stencil segments per batch
 
+// Candidates are staged as FP32 offsets from the bin's first atom.  The
+// membership test is made in FP32 against the list cutoffs widened by a
+// margin (1e-4 relative plus 1e-3 A^2 on r^2) several times larger than
+// the FP32 rounding of offsets of up to ~100 A, so no pair inside the cutoff is ever
+// missed; the few extra pairs just outside are rejected by the exact FP64
+// test every pass makes on every entry.
 __global__ void __launch_bounds__(BLOCK)
 k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start, Geo g,
        const double4* __restrict__ img_tab, double rp2, double rc2,
@@ -225,18 +231,20 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start, Geo
        uint32_t* __restrict__ list_c, int* __restrict__ cnt_c, int cap_c, int count_only,
        int* __restrict__ status)
 {
-    __shared__ double4 cand[LIST_TILE];
+    __shared__ float4 cand[LIST_TILE];
     __shared__ int seg_jb[LIST_MAXSEG], seg_img[LIST_MAXSEG], seg_off[LIST_MAXSEG + 1];
     __shared__ int sh[BLOCK];
 
     const int bin = blockIdx.x;
     const int s = bin_start[bin], e = bin_start[bin + 1];
     if (s == e) return;
+    const double4 origin = pos_s[s];
+    const float rp2f = (float)(rp2 * (1.0 + 1e-4) + 1e-3);
+    const float rc2f = (float)(rc2 * (1.0 + 1e-4) + 1e-3);
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
     const int nb0 = g.nb[0], nb1 = g.nb[1], nb2 = g.nb[2];
     const int b0 = bin % nb0, b1 = (bin / nb0) % nb1, b2 = bin / (nb0 * nb1);
-    const double rmax2 = rp2 > rc2 ? rp2 : rc2;
     const int n1 = 2 * g.timg[1] + 1, n2 = 2 * g.timg[2] + 1;
     const int n1r = 2 * g.reach[1] + 1, n2r = 2 * g.reach[2] + 1;
     const int nrows = n1r * n2r;
@@ -320,12 +328,14 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start, Geo
                 const double4 p = pos_s[j];
                 const double4 T = img_tab[img];
                 const uint32_t code = ((uint32_t)j << g.img_bits) | (uint32_t)img;
-                cand[t] = make_double4(p.x + T.x, p.y + T.y, p.z + T.z,
-                                       __hiloint2double(0, (int)code));
+                cand[t] = make_float4((float)(p.x + T.x - origin.x), (float)(p.y + T.y - origin.y),
+                                      (float)(p.z + T.z - origin.z), __int_as_float((int)code));
             }
             __syncthreads();
             for (int a = s + wv; a < e; a += WAVES_PER_BLOCK) {
                 const double4 pa = pos_s[a];
+                const float ax = (float)(pa.x - origin.x), ay = (float)(pa.y - origin.y),
+                            az = (float)(pa.z - origin.z);
                 const uint32_t self_code = ((uint32_t)a << g.img_bits) | (uint32_t)img_self;
                 int np = first ? 0 : cnt_p[a];
                 int nc = first ? 0 : cnt_c[a];
@@ -336,13 +346,13 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start, Geo
                     bool inp = false, inc = false;
                     uint32_t code = 0;
                     if (t < tn) {
-                        const double4 q = cand[t];
-                        const double dx = q.x - pa.x, dy = q.y - pa.y, dz = q.z - pa.z;
-                        const double r2 = dx * dx + dy * dy + dz * dz;
-                        code = (uint32_t)__double2loint(q.w);
-                        const bool ok = code != self_code && r2 < rmax2;
-                        inp = ok && r2 < rp2;
-                        inc = ok && r2 < rc2;
+                        const float4 q = cand[t];
+                        const float dx = q.x - ax, dy = q.y - ay, dz = q.z - az;
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        code = (uint32_t)__float_as_int(q.w);
+                        const bool ok = code != self_code;
+                        inp = ok && r2 < rp2f;
+                        inc = ok && r2 < rc2f;
                     }
                     const unsigned long long bp = __ballot(inp);
                     const unsigned long long bc = __ballot(inc);
