@@ -1,0 +1,34 @@
+"""Velocity-Verlet NVE reference driven by the C FP64 oracle's forces.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+One step: v += dt/2 F/m; x += dt v; F = F(x); v += dt/2 F/m, with
+positions in Angstrom, velocities in Angstrom/fs, masses in amu and forces
+in eV/Angstrom (1 eV/(Angstrom amu) = 9.648533212331e-3 Angstrom/fs^2).
+Parity: pinned through the force oracle; the integrator is the textbook
+scheme.
+"""
+
+import numpy as np
+
+from . import d3_ref
+
+ACC = 9.648533212331e-3
+KE = 103.642691
+
+
+def run(pos, vel, mass, types, cell, pbc, table, n_steps, dt, **prm):
+    pos = np.array(pos, dtype=np.float64)
+    vel = np.array(vel, dtype=np.float64)
+    m = np.asarray(mass, dtype=np.float64)[:, None]
+    res = d3_ref.d3(pos, types, cell, pbc, table, **prm)
+    f = res["forces"]
+    thermo = [(res["energy"], 0.5 * KE * float((m * vel * vel).sum()))]
+    for _ in range(n_steps):
+        vel += 0.5 * dt * ACC * f / m
+        pos += dt * vel
+        res = d3_ref.d3(pos, types, cell, pbc, table, **prm)
+        f = res["forces"]
+        vel += 0.5 * dt * ACC * f / m
+        thermo.append((res["energy"], 0.5 * KE * float((m * vel * vel).sum())))
+    return pos, vel, np.array(thermo)

@@ -622,6 +622,7 @@ int rebuild_grow(d3_ctx* c, const double* pos, hipStream_t s)
     std::memcpy(cell, c->cell, sizeof(cell));
     for (int k = 0; k < 3; k++) pbc[k] = c->geo.pbc[k];
     D3CHK(build(c, c->n, pos, c->type_copy.as<int32_t>(), cell, pbc, s));
+    c->n_rebuilds++;
     int st = 0;
     D3CHK(read_status(c, s, &st));
     if (st & ST_CAPACITY) {

@@ -69,8 +69,9 @@ struct d3_ctx {
     int* h_status = nullptr;
     hipStream_t last_stream = nullptr;
     d3::Surrogate* sur = nullptr;
-    // MD scratch
+    // MD scratch and the number of list rebuilds made by D3_AUTO_REBUILD
     d3::Buf md_scratch;
+    int64_t n_rebuilds = 0;
     // phase timing (events recorded around launch groups)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;

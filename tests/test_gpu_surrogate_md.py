@@ -1,0 +1,252 @@
+"""GPU tests of the learned C6 surrogate and of the NVE MD loop, through the
+C ABI, against the FP64 oracles (exact Eq. 3, the NumPy network reference,
+the C force oracle driving a NumPy velocity-Verlet loop)."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import d3_oracle as O
+from oracle import d3_ref as R
+from oracle import mlp_oracle as M
+from oracle import md_oracle
+
+pytestmark = pytest.mark.gpu
+
+TAB = synth.make_table()
+NE = 5
+NP = NE * (NE + 1) // 2
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    return torch
+
+
+def _pairs(ne=NE):
+    out = []
+    for e in range(ne):
+        for f in range(e, ne):
+            out.append((e, f))
+    return out
+
+
+def _queries(n, seed, cn_hi=6.0):
+    rng = np.random.default_rng(seed)
+    ei = rng.integers(0, NE, n).astype(np.int32)
+    ej = rng.integers(0, NE, n).astype(np.int32)
+    ni = rng.uniform(0, cn_hi, n)
+    nj = rng.uniform(0, cn_hi, n)
+    return ei, ej, ni, nj
+
+
+def _exact(calc, ei, ej, ni, nj):
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    dev = "cuda"
+    out = torch.zeros((len(ei), 3), dtype=torch.float64, device=dev)
+    d3.d3_c6_exact_eval(calc.ctx, torch.as_tensor(ei, device=dev), torch.as_tensor(ej, device=dev),
+                        torch.as_tensor(ni, device=dev), torch.as_tensor(nj, device=dev), out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _sur(calc, ei, ej, ni, nj, precision):
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    dev = "cuda"
+    out = torch.zeros((len(ei), 3), dtype=torch.float32, device=dev)
+    d3.d3_c6_surrogate_eval(calc.ctx, torch.as_tensor(ei, device=dev),
+                            torch.as_tensor(ej, device=dev),
+                            torch.as_tensor(ni, dtype=torch.float32, device=dev),
+                            torch.as_tensor(nj, dtype=torch.float32, device=dev), out,
+                            precision)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def test_exact_eq3_matches_oracle():
+    """The factorised Eq. 3 kernel (training labels, fallback) equals the
+    oracle's literal double sum and its derivatives."""
+    _torch()
+    from paper_2310_05279_amd import d3
+    calc = d3.D3(TAB)
+    ei, ej, ni, nj = _queries(4000, 1, cn_hi=7.0)
+    got = _exact(calc, ei, ej, ni, nj)
+    tab = O.convert_table(TAB)
+    c6, di, dj = O.c6_eq3(ei, ej, ni, nj, tab)
+    assert np.abs(got[:, 0] - c6).max() <= 1e-12 * np.abs(c6).max()
+    sc = np.abs(di).max()
+    assert np.abs(got[:, 1] - di).max() <= 1e-11 * sc
+    assert np.abs(got[:, 2] - dj).max() <= 1e-11 * sc
+    calc.close()
+
+
+def test_mfma_inference_matches_fp32_forward():
+    """The BF16-MFMA inference (split high/low operands, FP32 accumulation)
+    agrees with the FP32 reference forward on random weights; a wrong MFMA
+    lane layout would scramble the hidden units and fail this."""
+    _torch()
+    from paper_2310_05279_amd import d3
+    calc = d3.D3(TAB)
+    d3.d3_c6_surrogate_init(calc.ctx, 5)
+    ei, ej, ni, nj = _queries(5000, 2)
+    ref = _sur(calc, ei, ej, ni, nj, 0)
+    got = _sur(calc, ei, ej, ni, nj, 1)
+    scale = np.abs(ref).max(axis=0)
+    err = (np.abs(got - ref) / scale).max(axis=0)
+    print("mfma vs fp32 forward, relative max error per output:", err, flush=True)
+    assert np.all(err < 2e-5)
+    # the FP32 forward itself against the FP64 network reference
+    w = d3.d3_c6_surrogate_get_weights(calc.ctx)
+    cn_hi = float(w[-1])
+    for q in range(0, 5000, 250):
+        a, b = int(ei[q]), int(ej[q])
+        sw = a > b
+        e, f = (b, a) if sw else (a, b)
+        p = _pairs().index((e, f))
+        theta = w[p * M.N_PARAMS:(p + 1) * M.N_PARAMS].astype(np.float64)
+        xa, xb = 2 * ni[q] / cn_hi - 1, 2 * nj[q] / cn_hi - 1
+        y, _ = M.forward(theta, np.array([[xb, xa] if sw else [xa, xb]]))
+        st = w[NP * M.N_PARAMS + 6 * p: NP * M.N_PARAMS + 6 * p + 6]
+        y = y[0] * st[3:] + st[:3]
+        want = np.array([y[0], y[2], y[1]]) if sw else y
+        assert ref[q] == pytest.approx(want, rel=2e-5, abs=2e-5 * np.abs(want).max())
+    calc.close()
+
+
+def test_training_gradient_matches_oracle():
+    """The hand-written GPU backward pass equals the FP64 NumPy
+    backpropagation of the same network on the same samples."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    calc = d3.D3(TAB)
+    d3.d3_c6_surrogate_init(calc.ctx, 9)
+    rng = np.random.default_rng(3)
+    m = 700
+    pair = rng.integers(0, NP, m).astype(np.int32)
+    x = rng.uniform(-1, 1, (m, 2)).astype(np.float32)
+    y = rng.normal(size=(m, 3)).astype(np.float32)
+    g = torch.zeros((NP, M.N_PARAMS), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    d3.d3_c6_surrogate_grad(calc.ctx, torch.as_tensor(pair, device="cuda"),
+                            torch.as_tensor(x, device="cuda"), torch.as_tensor(y, device="cuda"),
+                            g, loss)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    w = d3.d3_c6_surrogate_get_weights(calc.ctx)
+    tot = 0.0
+    for p in range(NP):
+        sel = pair == p
+        theta = w[p * M.N_PARAMS:(p + 1) * M.N_PARAMS].astype(np.float64)
+        lp, gp = M.loss_and_grad(theta, x[sel].astype(np.float64), y[sel].astype(np.float64))
+        tot += lp * sel.sum()
+        err = np.abs(g[p] - gp).max() / np.abs(gp).max()
+        assert err < 2e-4, (p, err)
+    assert loss.item() == pytest.approx(tot / m, rel=1e-4)
+    calc.close()
+
+
+def _cn_hi(system):
+    res = R.d3(system["pos"], system["types"], system["cell"], system["pbc"], TAB)
+    return float(np.percentile(res["cn"], 99.9) + 0.5), res
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """Surrogate trained on 10^6 samples (config of the 200 000-atom cell:
+    CN box from the 99.9th CN percentile of a MOF-like cell + 0.5)."""
+    _torch()
+    from paper_2310_05279_amd import d3
+    m = synth.mof_like(3000, seed=31)
+    cn_hi, ref = _cn_hi(m)
+    calc = d3.D3(TAB)
+    d3.d3_c6_surrogate_init(calc.ctx, 5)
+    ei, ej, ni, nj = _queries(20000, 77, cn_hi)
+    exact = _exact(calc, ei, ej, ni, nj)
+    before = _sur(calc, ei, ej, ni, nj, 1)
+    loss = d3.d3_c6_surrogate_train(calc.ctx, n_samples=1_000_000, epochs=60, lr=3e-3,
+                                    lr_final=1e-5, seed=4, cn_hi=cn_hi)
+    after = _sur(calc, ei, ej, ni, nj, 1)
+    w = d3.d3_c6_surrogate_get_weights(calc.ctx)
+    calc.close()
+    return {"w": w, "loss": loss, "exact": exact, "before": before, "after": after,
+            "cn_hi": cn_hi, "mof": m, "ref": ref}
+
+
+def test_training_gain(trained):
+    """What the trained network gains over the untrained one: its error
+    against exact Eq. 3 on held-out CN pairs drops by orders of magnitude."""
+    ex, b, a = trained["exact"], trained["before"], trained["after"]
+    scale = np.abs(ex).max(axis=0)
+    eb = np.sqrt(np.mean((b - ex) ** 2, axis=0)) / scale
+    ea = np.sqrt(np.mean((a - ex) ** 2, axis=0)) / scale
+    print("final training loss %.3e; relative RMS error before %s after %s"
+          % (trained["loss"], eb, ea), flush=True)
+    assert np.all(ea < 0.05 * eb)
+    assert ea[0] < 2e-2
+
+
+def test_surrogate_forces_against_oracle(trained):
+    """Energy, forces and virial with the surrogate C6 against the FP64
+    oracle on a 3000-atom MOF-like cell (errors reported)."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    m, ref = trained["mof"], trained["ref"]
+    calc = d3.D3(TAB, mode="surrogate")
+    d3.d3_c6_surrogate_set_weights(calc.ctx, trained["w"])
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    out = calc.compute()
+    torch.cuda.synchronize()
+    calc.status()
+    n = m["pos"].shape[0]
+    de = abs(out["energy"].item() - ref["energy"]) / n
+    df = np.abs(out["forces"].cpu().numpy() - ref["forces"]).max()
+    dw = np.abs(out["virial"].cpu().numpy() - ref["virial"]).max()
+    print("surrogate vs oracle: |dE|/atom=%.3e max|dF|=%.3e (max|F|=%.3e) max|dW|=%.3e"
+          % (de, df, np.abs(ref["forces"]).max(), dw), flush=True)
+    assert np.isfinite(df) and df < 0.1 * np.abs(ref["forces"]).max()
+    calc.close()
+
+
+def test_weights_roundtrip():
+    _torch()
+    from paper_2310_05279_amd import d3
+    a = d3.D3(TAB)
+    d3.d3_c6_surrogate_init(a.ctx, 21)
+    w = d3.d3_c6_surrogate_get_weights(a.ctx)
+    b = d3.D3(TAB)
+    d3.d3_c6_surrogate_set_weights(b.ctx, w)
+    ei, ej, ni, nj = _queries(300, 5)
+    assert np.array_equal(_sur(a, ei, ej, ni, nj, 1), _sur(b, ei, ej, ni, nj, 1))
+    with pytest.raises(d3.D3Error):
+        d3.d3_c6_surrogate_set_weights(b.ctx, w[:-7])
+    a.close()
+    b.close()
+
+
+def test_md_nve_matches_oracle_integrator():
+    """20 velocity-Verlet steps (1 fs) of a 1000-atom MOF-like cell: GPU
+    positions, velocities and energies against the NumPy integrator driven
+    by the C oracle; lists rebuilt on the 1 A skin as needed."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    m = synth.mof_like(1000, seed=10)
+    vel, mass = synth.maxwell_velocities(m["types"], 300.0, seed=300)
+    vel = vel * 20.0  # hot start so that lists get rebuilt within 20 steps
+    calc = d3.D3(TAB, skin=1.0)
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    p = torch.as_tensor(m["pos"], device="cuda").clone()
+    v = torch.as_tensor(vel, device="cuda").clone()
+    ms = torch.as_tensor(mass, device="cuda")
+    thermo, rebuilds = d3.d3_md_nve(calc.ctx, 20, 1.0, p, v, ms, every=5)
+    rp, rv, rth = md_oracle.run(m["pos"], vel, mass, m["types"], m["cell"], m["pbc"], TAB, 20, 1.0)
+    dp = np.abs(p.cpu().numpy() - rp).max()
+    dv = np.abs(v.cpu().numpy() - rv).max()
+    print("md: rebuilds=%d max|dx|=%.2e max|dv|=%.2e" % (rebuilds, dp, dv), flush=True)
+    assert rebuilds >= 1
+    assert dp < 1e-9 and dv < 1e-10
+    assert thermo[:, 0] == pytest.approx(rth[::5, 0], rel=1e-9)
+    assert thermo[:, 1] == pytest.approx(rth[::5, 1], rel=1e-9)
+    calc.close()

@@ -482,3 +482,47 @@ def test_sampled_mode_matches_full():
     assert s["atom_energy"] == pytest.approx(full["atom_energy"][idx], rel=1e-11)
     assert s["cn"] == pytest.approx(full["cn"][idx], rel=1e-12)
     assert s["dedn"] == pytest.approx(full["dedn"][idx], rel=1e-10, abs=1e-14)
+
+
+# ------------------------------------------------- surrogate network ------
+
+def test_mlp_oracle_gradient_matches_finite_differences():
+    """The backpropagated loss gradient of the surrogate network equals
+    central differences of its loss, parameter by parameter."""
+    from oracle import mlp_oracle as M
+    rng = np.random.default_rng(0)
+    theta = rng.normal(0.0, 0.4, M.N_PARAMS)
+    x = rng.uniform(-1, 1, (17, 2))
+    t = rng.normal(size=(17, 3))
+    loss, g = M.loss_and_grad(theta, x, t)
+    h = 1e-6
+    idx = np.concatenate([np.arange(0, 64, 7), np.arange(64, 96, 5), np.arange(96, 1120, 97),
+                          np.arange(1120, 1152, 9), np.arange(1152, 1251, 11)])
+    for q in idx:
+        tp = theta.copy()
+        tp[q] += h
+        tm = theta.copy()
+        tm[q] -= h
+        fd = (M.loss_and_grad(tp, x, t)[0] - M.loss_and_grad(tm, x, t)[0]) / (2 * h)
+        assert g[q] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_mlp_oracle_closed_forms():
+    """Networks with a closed-form output: biases only give y = b3; a
+    constant hidden layer gives y = silu(c) W3 column sums; silu(0) = 0 and
+    silu(z) -> z for large z."""
+    from oracle import mlp_oracle as M
+    p = M.unpack(np.zeros(M.N_PARAMS)).copy()
+    p = {k: v.copy() for k, v in p.items()}
+    p["b3"][:] = [0.5, -1.0, 2.0]
+    y, _ = M.forward(M.pack(p), np.array([[0.3, -0.7], [1.0, 1.0]]))
+    assert np.all(y == np.array([0.5, -1.0, 2.0]))
+    p["b2"][:] = 1.3
+    p["W3"][:, 0] = 1.0 / 32
+    p["W3"][:, 1] = 0.0
+    p["W3"][:, 2] = -2.0 / 32
+    y, _ = M.forward(M.pack(p), np.array([[0.1, 0.2]]))
+    s = 1.3 / (1.0 + np.exp(-1.3))
+    assert y[0] == pytest.approx([0.5 + s, -1.0, 2.0 - 2.0 * s], rel=1e-14)
+    assert M.silu(np.array([0.0]))[0] == 0.0
+    assert M.silu(np.array([40.0]))[0] == pytest.approx(40.0, rel=1e-15)
