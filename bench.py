@@ -7,9 +7,11 @@ reductions, i.e. energy, forces and virial of the cell.  The headline
 workload is the 24 000-atom MOF-like cell (H,C,N,O,Zn 4:6:1:2:1 at 0.04
 atoms/A^3, R_pot = 12 A, R_cn = 6 A) in the plain FP64 form; inputs are
 resident in HBM before timing starts.  Extra fields report the FP32
-precision form and the surrogate form on the same cell, the evaluation
-alone (lists reused as in MD), and the 10^6-atom MOF-like and
-500 000-atom bilayer cells.
+precision form and the learned-C6 surrogate form on the same cell (with
+their force deviation from the plain form), the evaluation alone (lists
+reused as in MD), the 200 000-atom and 10^6-atom MOF-like cells, the
+500 000-atom bilayer, and velocity-Verlet NVE on the 10^6-atom cell (300 K,
+1 fs, 1 A skin) in all three forms with its total-energy drift.
 
 Prints ONE JSON line.  Usage: python bench.py [--steps K] [--warmup W]
 """
@@ -30,6 +32,33 @@ METRIC = ("D3 atom-steps/s (E+F+virial), surrogate/FP32 vs plain at "
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
+
+
+# HBM bytes per launch of the dispersion pass on the 24 000-atom cell, from
+# two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch), each scaled by what the same counter read for a 512 MiB device
+# copy (FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  The figure belongs to the
+# kernel sources it was taken with: when their hash differs it is not used.
+PAIR_TRAFFIC = {"fetch_kib": 24249.878, "write_kib": 1129.841,
+                "fetch_scale": 1.99990, "write_scale": 1.0,
+                "sources": ("disp.hip", "d3_device.h", "d3_internal.h"),
+                "sha256": "4e2ac591a5fb3f1310908510e2c6efd3"}
+
+
+def _sources_hash(names):
+    import hashlib
+    h = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_2310_05279_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:32]
+
+
+def pair_traffic_bytes():
+    t = PAIR_TRAFFIC
+    if _sources_hash(t["sources"]) != t["sha256"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
 def _flops_per_pair(ki, kj):
@@ -125,7 +154,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the precision/surrogate/large-cell fields")
+                    help="skip the precision/surrogate/large-cell/MD fields")
+    ap.add_argument("--sur-epochs", type=int, default=300)
+    ap.add_argument("--md-steps", type=int, default=200)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run 3 plain device-to-device copies of this many MiB "
+                         "(a known-size reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the D3 path here is single-GPU "
@@ -137,6 +171,13 @@ def main():
     import synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     table = synth.make_table()
     system = synth.mof_like(24000)
     n = system["pos"].shape[0]
@@ -160,9 +201,13 @@ def main():
     achieved = flops / (pair_ms * 1e-3) / 1e12
     roofline = {"kernel": "k_pair<fp64> (dispersion pass)", "bound": "alu",
                 "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": pair_traffic_bytes(),
                 "algorithmic_flops_per_launch": flops, "unique_pairs": npairs,
                 "avg_kernel_ms": pair_ms}
+    if roofline["traffic"] is not None:
+        gbs = roofline["traffic"] / (pair_ms * 1e-3) / 1e9
+        roofline["hbm_GBs"] = gbs
+        roofline["hbm_frac"] = gbs / HBM_PEAK_GBS
 
     extra = {"ms_per_step_eval_only": ms_eval,
              "atom_steps_per_s_eval_only": n / (ms_eval * 1e-3),
@@ -182,18 +227,77 @@ def main():
                              "max_abs_dF_vs_plain": float(np.abs(fp - res_f).max()),
                              "abs_dE_per_atom_vs_plain": abs(ep - res_e) / n,
                              "max_abs_dW_vs_plain": float(np.abs(wp - res_w).max())}
-        for name, big, steps in (("mof_1M", synth.mof_like(1_000_000), 10),
-                                 ("graphene_500k", synth.bilayer_graphene(250, 500, seed=500000), 10)):
+        # learned C6 surrogate: trained on 10^6 exact-labelled CN pairs over the
+        # CN box [0, 99.9th percentile + 0.5]^2 of this cell, then timed
+        from paper_2310_05279_amd import d3 as d3mod
+        run = Runner(system, table, "surrogate")
+        cn = run.calc.coordination().cpu().numpy()
+        cn_hi = float(np.percentile(cn, 99.9) + 0.5)
+        d3mod.d3_c6_surrogate_init(run.calc.ctx, 5)
+        t0 = time.perf_counter()
+        loss = d3mod.d3_c6_surrogate_train(run.calc.ctx, n_samples=1_000_000,
+                                           epochs=args.sur_epochs, lr=5e-3, lr_final=1e-6,
+                                           seed=4, cn_hi=cn_hi)
+        t_train = time.perf_counter() - t0
+        weights = d3mod.d3_c6_surrogate_get_weights(run.calc.ctx)
+        ms_s = run.timed(max(10, args.steps // 4), 3)
+        phs = run.phases(10)
+        fsu = run.out["forces"].cpu().numpy()
+        esu = float(run.out["energy"].item())
+        run.close()
+        extra["surrogate"] = {"atom_steps_per_s": n / (ms_s * 1e-3), "ms_per_step": ms_s,
+                              "phase_ms": phs, "train_s": t_train, "train_loss": loss,
+                              "cn_hi": cn_hi,
+                              "max_abs_dF_vs_plain": float(np.abs(fsu - res_f).max()),
+                              "abs_dE_per_atom_vs_plain": abs(esu - res_e) / n,
+                              "speed_vs_plain": ms / ms_s}
+        print("[bench] surrogate %s" % json.dumps(extra["surrogate"]), file=sys.stderr, flush=True)
+
+        def forms(big, steps, modes):
             entry = {}
-            for mode in ("plain", "prec"):
+            for mode in modes:
                 run = Runner(big, table, mode)
+                if mode == "surrogate":
+                    d3mod.d3_c6_surrogate_set_weights(run.calc.ctx, weights)
                 msb = run.timed(steps, 2)
                 phb = run.phases(5)
                 run.close()
                 entry[mode] = {"atom_steps_per_s": big["pos"].shape[0] / (msb * 1e-3),
                                "ms_per_step": msb, "phase_ms": phb}
-            extra[name] = entry
-            print("[bench] %s %s" % (name, json.dumps(entry)), file=sys.stderr, flush=True)
+            return entry
+
+        for name, big, steps, modes in (
+                ("mof_200k", synth.mof_like(200_000), 10, ("plain", "prec", "surrogate")),
+                ("mof_1M", synth.mof_like(1_000_000), 10, ("plain", "prec")),
+                ("graphene_500k", synth.bilayer_graphene(250, 500, seed=500000), 10,
+                 ("plain", "prec"))):
+            extra[name] = forms(big, steps, modes)
+            print("[bench] %s %s" % (name, json.dumps(extra[name])), file=sys.stderr, flush=True)
+
+        # velocity-Verlet NVE on the 10^6-atom cell: 300 K Maxwell start, 1 fs,
+        # lists with a 1 A skin rebuilt when an atom moved more than 0.5 A
+        big = synth.mof_like(1_000_000)
+        vel0, mass = synth.maxwell_velocities(big["types"], 300.0, seed=300)
+        md = {}
+        for mode in ("plain", "prec", "surrogate"):
+            run = Runner(big, table, mode, skin=1.0)
+            if mode == "surrogate":
+                d3mod.d3_c6_surrogate_set_weights(run.calc.ctx, weights)
+            pos = run.calc.pos.clone()
+            vel = torch.as_tensor(vel0, device="cuda")
+            mss = torch.as_tensor(mass, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            thermo, reb = d3mod.d3_md_nve(run.calc.ctx, args.md_steps, 1.0, pos, vel, mss,
+                                          every=args.md_steps)
+            dt = time.perf_counter() - t0
+            run.close()
+            nb = big["pos"].shape[0]
+            md[mode] = {"atom_steps_per_s": nb * args.md_steps / dt,
+                        "ms_per_step": 1e3 * dt / args.md_steps, "rebuilds": reb,
+                        "etot_drift_per_atom_eV": float((thermo[-1, 2] - thermo[0, 2]) / nb)}
+        extra["md_nve_mof_1M"] = md
+        print("[bench] md %s" % json.dumps(md), file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -5,8 +5,9 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 One step: v += dt/2 F/m; x += dt v; F = F(x); v += dt/2 F/m, with
 positions in Angstrom, velocities in Angstrom/fs, masses in amu and forces
 in eV/Angstrom (1 eV/(Angstrom amu) = 9.648533212331e-3 Angstrom/fs^2).
-Parity: pinned through the force oracle; the integrator is the textbook
-scheme.
+Parity: the forces are the pinned force oracle's; the integrator is pinned
+by second-order energy conservation on a smooth cluster (the error falls
+as dt^2) and by time reversibility.
 """
 
 import numpy as np

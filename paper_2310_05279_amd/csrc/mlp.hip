@@ -39,7 +39,7 @@ static_assert(OB3 + 3 == NPAR, "parameter layout");
 constexpr int SM_W1 = 0, SM_B1 = 2 * H, SM_B2 = 3 * H, SM_W3 = 4 * H, SM_B3 = 7 * H;
 constexpr int SMALL = 7 * H + 4;  // W1, b1, b2, W3, b3 (+pad) per pair, FP32
 constexpr int TB = 256;           // training samples per pair per step
-constexpr int SUR_CAP = 448;      // list entries per atom the surrogate pass sorts in LDS
+constexpr int SUR_CAP = 448;      // list entries per atom sorted in LDS at a time
 constexpr int MAXPAIR = MAXELEM * (MAXELEM + 1) / 2;
 constexpr int SUR_ELEM = 8;       // elements the surrogate dispersion pass supports
 constexpr int SUR_PAIR = SUR_ELEM * (SUR_ELEM + 1) / 2;
@@ -621,114 +621,121 @@ k_pair_sur(int n, const double4* __restrict__ pos_s, const double4* __restrict__
         const double4 pi = pos_s[i];
         const int zi = __builtin_amdgcn_readfirstlane(zbits(pi.w));
         const double ni = cn[i];
-        const int cnt = min(min(cnt_p[i], cap_p), SUR_CAP);
-        const uint32_t* lp = list_p + (size_t)i * cap_p;
-        // pass 1: codes to LDS, element tallies
-        int tally[SUR_ELEM];
-#pragma unroll
-        for (int f = 0; f < SUR_ELEM; f++) tally[f] = 0;
-        for (int k0 = 0; k0 < cnt; k0 += WAVE) {
-            const int k = k0 + lane;
-            const uint32_t code = list_code(lp, k, cnt, cap_p);
-            const int zj = zbits(pos_s[code >> img_bits].w);
-            if (k < cnt) s_raw[wv][k] = code;
-#pragma unroll
-            for (int f = 0; f < SUR_ELEM; f++)
-                if (f < ne) tally[f] += __popcll(__ballot(k < cnt && zj == f));
-        }
-        // pass 2: stable partition by element
-        int off[SUR_ELEM];
-        {
-            int o = 0;
-#pragma unroll
-            for (int f = 0; f < SUR_ELEM; f++) {
-                off[f] = o;
-                o += (f < ne) ? tally[f] : 0;
-                if (lane == 0) s_tally[wv][f] = tally[f];
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int k0 = 0; k0 < cnt; k0 += WAVE) {
-            const int k = k0 + lane;
-            const uint32_t code = k < cnt ? s_raw[wv][k] : 0u;
-            const int zj = zbits(pos_s[code >> img_bits].w);
-#pragma unroll
-            for (int f = 0; f < SUR_ELEM; f++) {
-                if (f < ne) {
-                    const unsigned long long b = __ballot(k < cnt && zj == f);
-                    if (k < cnt && zj == f) s_srt[wv][off[f] + __popcll(b & lanemask)] = code;
-                    off[f] += __popcll(b);
-                }
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
+        const int cnt_all = min(cnt_p[i], cap_p);
+        const uint32_t* row = list_p + (size_t)i * cap_p;
         double fx = 0.0, fy = 0.0, fz = 0.0, ue = 0.0, g = 0.0;
-        int base = 0;
-        for (int f = 0; f < ne; f++) {
-            const int cf = __builtin_amdgcn_readfirstlane(s_tally[wv][f]);
-            if (cf == 0) continue;
-            int p;
-            bool sw;
-            order_query(zi, f, ne, &p, &sw);
-            const float* sm = s_small + p * SMALL;
-            bf16x8 ah[2], al[2];
-            for (int blk = 0; blk < 2; blk++) {
-                ah[blk] = sv.a_hi[((size_t)p * 2 + blk) * WAVE + lane];
-                al[blk] = sv.a_lo[((size_t)p * 2 + blk) * WAVE + lane];
+        // the list is taken in chunks of at most SUR_CAP entries
+        for (int c0 = 0; c0 < cnt_all; c0 += SUR_CAP) {
+            const int cnt = min(cnt_all - c0, SUR_CAP);
+            const uint32_t* lp = row + c0;
+            const int capr = cap_p - c0;
+            // pass 1: codes to LDS, element tallies
+            int tally[SUR_ELEM];
+#pragma unroll
+            for (int f = 0; f < SUR_ELEM; f++) tally[f] = 0;
+            for (int k0 = 0; k0 < cnt; k0 += WAVE) {
+                const int k = k0 + lane;
+                const uint32_t code = list_code(lp, k, cnt, capr);
+                const int zj = zbits(pos_s[code >> img_bits].w);
+                if (k < cnt) s_raw[wv][k] = code;
+#pragma unroll
+                for (int f = 0; f < SUR_ELEM; f++)
+                    if (f < ne) tally[f] += __popcll(__ballot(k < cnt && zj == f));
             }
-            const float* st = sv.stats + 6 * p;
-            const float st0 = st[0], st1 = st[1], st2 = st[2], st3 = st[3], st4 = st[4],
-                        st5 = st[5];
-            const double4 c = s_pc[zi * SUR_ELEM + f];
-            for (int it = 0; it < cf; it += WAVE) {
-                const bool valid = it + lane < cf;
-                const uint32_t code = valid ? s_srt[wv][base + it + lane] : 0u;
-                const uint32_t j = code >> img_bits;
-                const double4 pj = pos_s[j];
-                const double nj = cn[j];
-                const double4 T = image<IMG>(s_img, img_tab, code & img_mask);
-                const double dx = pj.x + T.x - pi.x;
-                const double dy = pj.y + T.y - pi.y;
-                const double dz = pj.z + T.z - pi.z;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const bool in = valid && r2 < sc.rp2;
-                const float xa = (float)(2.0 * ni / cn_hi - 1.0);
-                const float xb = (float)(2.0 * nj / cn_hi - 1.0);
-                float y[3];
-                mlp64(sw ? xb : xa, sw ? xa : xb, sm, ah, al, y);
-                float c6 = y[0] * st3 + st0;
-                const float da = y[1] * st4 + st1, db = y[2] * st5 + st2;
-                float dc6 = sw ? db : da;
-                if (ni > (double)cn_hi || nj > (double)cn_hi) {
-                    double ex[3];  // exact Eq. 3 outside the trained box
-                    exact_c6(tab, c6ref, zi, f, ni, nj, ex);
-                    c6 = (float)ex[0];
-                    dc6 = (float)ex[1];
+            // pass 2: stable partition by element
+            int off[SUR_ELEM];
+            {
+                int o = 0;
+#pragma unroll
+                for (int f = 0; f < SUR_ELEM; f++) {
+                    off[f] = o;
+                    o += (f < ne) ? tally[f] : 0;
+                    if (lane == 0) s_tally[wv][f] = tally[f];
                 }
-                c6 = in ? c6 : 0.0f;
-                dc6 = in ? dc6 : 0.0f;
-                const float x = (float)dx, yv = (float)dy, zz = (float)dz;
-                const float q2 = (float)r2;
-                const float r4 = q2 * q2, r6 = r4 * q2, r8 = r4 * r4;
-                const float t6 = __frcp_rn(r6 + (float)c.x), t8 = __frcp_rn(r8 + (float)c.y);
-                const float a6 = (float)sc.s6 * t6, a8 = (float)c.w * t8;
-                const float gg = a6 + a8;
-                const float dphi_r = c6 * (6.0f * a6 * r4 * t6 + 8.0f * a8 * r6 * t8);
-                ue += (double)(-0.5f * c6 * gg);
-                g += (double)(-gg * dc6);
-                fx += (double)(dphi_r * x);
-                fy += (double)(dphi_r * yv);
-                fz += (double)(dphi_r * zz);
-                const float hh = -0.5f * dphi_r;
-                const float hx = hh * x, hy = hh * yv;
-                vir[0] += (double)(hx * x);
-                vir[1] += (double)(hx * yv);
-                vir[2] += (double)(hx * zz);
-                vir[3] += (double)(hy * yv);
-                vir[4] += (double)(hy * zz);
-                vir[5] += (double)(hh * zz * zz);
             }
-            base += cf;
+            __builtin_amdgcn_wave_barrier();
+            for (int k0 = 0; k0 < cnt; k0 += WAVE) {
+                const int k = k0 + lane;
+                const uint32_t code = k < cnt ? s_raw[wv][k] : 0u;
+                const int zj = zbits(pos_s[code >> img_bits].w);
+#pragma unroll
+                for (int f = 0; f < SUR_ELEM; f++) {
+                    if (f < ne) {
+                        const unsigned long long b = __ballot(k < cnt && zj == f);
+                        if (k < cnt && zj == f) s_srt[wv][off[f] + __popcll(b & lanemask)] = code;
+                        off[f] += __popcll(b);
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            int base = 0;
+            for (int f = 0; f < ne; f++) {
+                const int cf = __builtin_amdgcn_readfirstlane(s_tally[wv][f]);
+                if (cf == 0) continue;
+                int p;
+                bool sw;
+                order_query(zi, f, ne, &p, &sw);
+                const float* sm = s_small + p * SMALL;
+                bf16x8 ah[2], al[2];
+                for (int blk = 0; blk < 2; blk++) {
+                    ah[blk] = sv.a_hi[((size_t)p * 2 + blk) * WAVE + lane];
+                    al[blk] = sv.a_lo[((size_t)p * 2 + blk) * WAVE + lane];
+                }
+                const float* st = sv.stats + 6 * p;
+                const float st0 = st[0], st1 = st[1], st2 = st[2], st3 = st[3], st4 = st[4],
+                            st5 = st[5];
+                const double4 c = s_pc[zi * SUR_ELEM + f];
+                for (int it = 0; it < cf; it += WAVE) {
+                    const bool valid = it + lane < cf;
+                    const uint32_t code = valid ? s_srt[wv][base + it + lane] : 0u;
+                    const uint32_t j = code >> img_bits;
+                    const double4 pj = pos_s[j];
+                    const double nj = cn[j];
+                    const double4 T = image<IMG>(s_img, img_tab, code & img_mask);
+                    const double dx = pj.x + T.x - pi.x;
+                    const double dy = pj.y + T.y - pi.y;
+                    const double dz = pj.z + T.z - pi.z;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    const bool in = valid && r2 < sc.rp2;
+                    const float xa = (float)(2.0 * ni / cn_hi - 1.0);
+                    const float xb = (float)(2.0 * nj / cn_hi - 1.0);
+                    float y[3];
+                    mlp64(sw ? xb : xa, sw ? xa : xb, sm, ah, al, y);
+                    float c6 = y[0] * st3 + st0;
+                    const float da = y[1] * st4 + st1, db = y[2] * st5 + st2;
+                    float dc6 = sw ? db : da;
+                    if (ni > (double)cn_hi || nj > (double)cn_hi) {
+                        double ex[3];  // exact Eq. 3 outside the trained box
+                        exact_c6(tab, c6ref, zi, f, ni, nj, ex);
+                        c6 = (float)ex[0];
+                        dc6 = (float)ex[1];
+                    }
+                    c6 = in ? c6 : 0.0f;
+                    dc6 = in ? dc6 : 0.0f;
+                    const float x = (float)dx, yv = (float)dy, zz = (float)dz;
+                    const float q2 = (float)r2;
+                    const float r4 = q2 * q2, r6 = r4 * q2, r8 = r4 * r4;
+                    const float t6 = __frcp_rn(r6 + (float)c.x), t8 = __frcp_rn(r8 + (float)c.y);
+                    const float a6 = (float)sc.s6 * t6, a8 = (float)c.w * t8;
+                    const float gg = a6 + a8;
+                    const float dphi_r = c6 * (6.0f * a6 * r4 * t6 + 8.0f * a8 * r6 * t8);
+                    ue += (double)(-0.5f * c6 * gg);
+                    g += (double)(-gg * dc6);
+                    fx += (double)(dphi_r * x);
+                    fy += (double)(dphi_r * yv);
+                    fz += (double)(dphi_r * zz);
+                    const float hh = -0.5f * dphi_r;
+                    const float hx = hh * x, hy = hh * yv;
+                    vir[0] += (double)(hx * x);
+                    vir[1] += (double)(hx * yv);
+                    vir[2] += (double)(hx * zz);
+                    vir[3] += (double)(hy * yv);
+                    vir[4] += (double)(hy * zz);
+                    vir[5] += (double)(hh * zz * zz);
+                }
+                base += cf;
+            }
+            __builtin_amdgcn_wave_barrier();  // LDS rows are reused by the next chunk
         }
         fx = wave_sum(fx);
         fy = wave_sum(fy);
@@ -851,9 +858,6 @@ int surrogate_pair(d3_ctx* c, const PairScal& sc, hipStream_t st)
 {
     if (!c->sur || !c->sur->trained)
         return fail(D3_ERR_NOT_TRAINED, "surrogate mode before training or loading weights");
-    if (c->cap_p > SUR_CAP)
-        return fail(D3_ERR_CAPACITY, "surrogate pass sorts at most %d list entries per atom (list "
-                                     "capacity %d)", SUR_CAP, c->cap_p);
     if (c->n_elem > SUR_ELEM)
         return fail(D3_ERR_INVALID_ARG, "surrogate pass supports at most %d elements", SUR_ELEM);
     const int n = (int)c->n;
