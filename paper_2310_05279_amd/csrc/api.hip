@@ -263,11 +263,13 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
     launch_scatter(n, c->bin_of.as<int>(), c->bin_start.as<int>(), fill, c->perm_tmp.as<int>(), s);
     launch_rank(n, c->perm_tmp.as<int>(), c->bin_of.as<int>(), c->bin_start.as<int>(), pos,
                 c->type_copy.as<int32_t>(), c->shift.as<double4>(), c->perm.as<int>(),
-                c->pos_s.as<double4>(), c->shift_s.as<double4>(), c->ref_s.as<double4>(), s);
+                c->pos_s.as<double4>(), c->shift_s.as<double4>(), c->ref_s.as<double4>(),
+                g.nbins, c->slab.as<int>(), s);
     HIPCHK(hipGetLastError());
     const double rp = c->prm.r_pot + c->prm.skin, rcn = c->prm.r_cn + c->prm.skin;
     if (size_lists) {
-        launch_list(n, c->pos_s.as<double4>(), c->bin_start.as<int>(), g, c->img_tab.as<double4>(),
+        launch_list(n, c->pos_s.as<double4>(), c->bin_start.as<int>(), c->slab.as<int>(), g,
+                    c->img_tab.as<double4>(),
                     rp * rp, rcn * rcn, nullptr, c->cnt_p.as<int>(), 0, nullptr,
                     c->cnt_c.as<int>(), 0, 1, c->status.as<int>(), s);
         HIPCHK(hipGetLastError());
@@ -282,7 +284,8 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
         D3CHK(ensure(c->list_p, N * c->cap_p * sizeof(uint32_t)));
         D3CHK(ensure(c->list_c, N * c->cap_c * sizeof(uint32_t)));
     }
-    launch_list(n, c->pos_s.as<double4>(), c->bin_start.as<int>(), g, c->img_tab.as<double4>(),
+    launch_list(n, c->pos_s.as<double4>(), c->bin_start.as<int>(), c->slab.as<int>(), g,
+                c->img_tab.as<double4>(),
                 rp * rp, rcn * rcn, c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p,
                 c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, 0, c->status.as<int>(), s);
     HIPCHK(hipGetLastError());
@@ -322,6 +325,7 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
         D3CHK(alloc_atoms(c, n));
         D3CHK(ensure(c->count, 2 * (size_t)g.nbins * sizeof(int)));
         D3CHK(ensure(c->bin_start, ((size_t)g.nbins + 1) * sizeof(int)));
+        D3CHK(ensure(c->slab, 16 * sizeof(int)));
         D3CHK(ensure(c->scan_tmp, ((size_t)g.nbins / 1024 + 4) * sizeof(int)));
         D3CHK(ensure(c->img_tab, imgs.size() * sizeof(double4)));
         HIPCHK(hipMemcpyAsync(c->img_tab.p, imgs.data(), imgs.size() * sizeof(double4),

@@ -9,12 +9,11 @@
 // fastest along the first lattice vector, so one stencil row of bins is one
 // contiguous range of sorted atoms.
 //
-// One workgroup builds the lists of all atoms of one bin.  The atoms of
-// the bin's stencil (its candidates) are staged once into LDS with their
-// image translation already added; each wave then tests one atom of the
-// bin against the staged candidates, 64 per step, and compacts the hits
-// with a ballot.  Stencils that do not fit in LDS are processed in tiles.
-#include "d3_internal.h"
+// Bins are at least a third of the list cutoff wide, so the stencil is 7
+// bins along each axis.  One wave builds the lists of all atoms of one bin
+// (see k_list); the bins are split between the XCDs in slabs that hold
+// equal shares of the atoms.
+#include "d3_device.h"
 
 namespace d3 {
 
@@ -176,7 +175,7 @@ k_rank(int n, const int* __restrict__ perm_tmp, const int* __restrict__ bin_of,
        const int* __restrict__ bin_start, const double* __restrict__ pos,
        const int32_t* __restrict__ type_copy, const double4* __restrict__ shift,
        int* __restrict__ perm, double4* __restrict__ pos_s, double4* __restrict__ shift_s,
-       double4* __restrict__ ref_s)
+       double4* __restrict__ ref_s, int nbins, int* __restrict__ slab)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -186,6 +185,12 @@ k_rank(int n, const int* __restrict__ perm_tmp, const int* __restrict__ bin_of,
     int rank = 0;
     for (int q = s; q < e; q++) rank += (perm_tmp[q] < v) ? 1 : 0;
     const int o = s + rank;
+    // XCD slabs of bins holding equal shares of the sorted atoms: slab x
+    // starts at the bin of sorted atom floor(n x / 8)
+#pragma unroll
+    for (int x = 0; x < 8; x++)
+        if (o == (int)((long long)n * x / 8)) slab[x] = b;
+    if (o == 0) slab[8] = nbins;
     const double4 sh = shift[v];
     const double x = pos[3 * v] + sh.x, y = pos[3 * v + 1] + sh.y, z = pos[3 * v + 2] + sh.z;
     perm[o] = v;
@@ -215,175 +220,190 @@ k_update(int n, const double* __restrict__ pos, const int* __restrict__ perm,
     pos_s[k] = make_double4(x, y, z, p.w);
 }
 
-constexpr int LIST_TILE = 2048;  // staged candidates per LDS tile
-constexpr int LIST_MAXSEG = 512; // stencil segments per batch
+constexpr int LIST_AHEAD = 4;  // candidate steps whose loads are in flight together
 
-// Candidates are staged as FP32 offsets from the bin's first atom.  The
-// membership test is made in FP32 against the list cutoffs widened by a
-// margin (1e-4 relative plus 1e-3 A^2 on r^2) several times larger than
-// the FP32 rounding of offsets of up to ~100 A, so no pair inside the cutoff is ever
-// missed; the few extra pairs just outside are rejected by the exact FP64
-// test every pass makes on every entry.
+// number of set bits of m below this lane
+__device__ __forceinline__ int lanes_below(unsigned long long m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const int t = __shfl_up(v, d, WAVE);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// One wave builds the lists of all atoms of one bin.  The bin's stencil is
+// cut into segments, one per stencil row and periodic image; each segment is
+// one contiguous range of sorted atoms.  Lanes take the segments' candidates
+// densely packed, 64 per step (a lane finds its segment by a binary search
+// over the segment offsets held by the lanes), load each candidate once, and
+// test it in FP64 against every atom of the bin in turn; hits are compacted
+// with a ballot into the atom's row.  The test is the same FP64 arithmetic
+// as the passes, with a 1e-12 relative widening so that no pair a pass would
+// accept is missed; the passes make the exact decision.  COUNT: count only.
+template <bool IMG, bool COUNT>
 __global__ void __launch_bounds__(BLOCK)
-k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start, Geo g,
+k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
+       const int* __restrict__ slab, Geo g,
        const double4* __restrict__ img_tab, double rp2, double rc2,
        uint32_t* __restrict__ list_p, int* __restrict__ cnt_p, int cap_p,
-       uint32_t* __restrict__ list_c, int* __restrict__ cnt_c, int cap_c, int count_only,
+       uint32_t* __restrict__ list_c, int* __restrict__ cnt_c, int cap_c,
        int* __restrict__ status)
 {
-    __shared__ float4 cand[LIST_TILE];
-    __shared__ int seg_jb[LIST_MAXSEG], seg_img[LIST_MAXSEG], seg_off[LIST_MAXSEG + 1];
-    __shared__ int sh[BLOCK];
-
-    const int bin = blockIdx.x;
-    const int s = bin_start[bin], e = bin_start[bin + 1];
-    if (s == e) return;
-    const double4 origin = pos_s[s];
-    const float rp2f = (float)(rp2 * (1.0 + 1e-4) + 1e-3);
-    const float rc2f = (float)(rc2 * (1.0 + 1e-4) + 1e-3);
+    __shared__ double4 s_img[IMG ? IMG_LDS : 1];
+    load_images<IMG>(s_img, img_tab, g.n_img);
+    __syncthreads();
+    const double rp2w = rp2 * (1.0 + 1e-12), rc2w = rc2 * (1.0 + 1e-12);
     const int lane = threadIdx.x & (WAVE - 1);
-    const int wv = threadIdx.x / WAVE;
     const int nb0 = g.nb[0], nb1 = g.nb[1], nb2 = g.nb[2];
-    const int b0 = bin % nb0, b1 = (bin / nb0) % nb1, b2 = bin / (nb0 * nb1);
     const int n1 = 2 * g.timg[1] + 1, n2 = 2 * g.timg[2] + 1;
     const int n1r = 2 * g.reach[1] + 1, n2r = 2 * g.reach[2] + 1;
     const int nrows = n1r * n2r;
-    int ua = b0 - g.reach[0], ub = b0 + g.reach[0], ta0, ta1;
-    if (g.pbc[0]) {
-        ta0 = floordiv(ua, nb0);
-        ta1 = floordiv(ub, nb0);
-    } else {
-        ua = ua < 0 ? 0 : ua;
-        ub = ub >= nb0 ? nb0 - 1 : ub;
-        ta0 = ta1 = 0;
-    }
-    const int spr = ta1 - ta0 + 1;  // segments per row
-    int rpb = LIST_MAXSEG / spr;
-    rpb = rpb < 1 ? 1 : (rpb > BLOCK ? BLOCK : rpb);
-    const int img_self = (g.timg[0] * n1 + g.timg[1]) * n2 + g.timg[2];
-    const unsigned long long lanemask = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-    bool first = true;
-
-    for (int r0 = 0; r0 < nrows; r0 += rpb) {
-        const int rcount = (nrows - r0) < rpb ? (nrows - r0) : rpb;
-        if ((int)threadIdx.x < rcount) {
-            const int r = r0 + threadIdx.x;
-            const int u1 = b1 + (r % n1r - g.reach[1]);
-            const int u2 = b2 + (r / n1r - g.reach[2]);
-            int t1 = 0, w1 = u1, t2 = 0, w2 = u2;
-            bool ok = true;
-            if (g.pbc[1]) { t1 = floordiv(u1, nb1); w1 = u1 - t1 * nb1; }
-            else if (u1 < 0 || u1 >= nb1) ok = false;
-            if (g.pbc[2]) { t2 = floordiv(u2, nb2); w2 = u2 - t2 * nb2; }
-            else if (u2 < 0 || u2 >= nb2) ok = false;
-            for (int q = 0; q < spr; q++) {
-                const int slot = threadIdx.x * spr + q;
+    const uint32_t img_self = (uint32_t)((g.timg[0] * n1 + g.timg[1]) * n2 + g.timg[2]);
+    // the waves of XCD x take the bins of slab x round-robin
+    const int per = gridDim.x >> 3;
+    const int lb = xcd_block();
+    const int x = lb / per;
+    const int wave0 = (lb - x * per) * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
+    const int bin_lo = __builtin_amdgcn_readfirstlane(slab[x]);
+    const int bin_hi = __builtin_amdgcn_readfirstlane(slab[x + 1]);
+    for (int bin = __builtin_amdgcn_readfirstlane(bin_lo + wave0); bin < bin_hi;
+         bin += per * WAVES_PER_BLOCK) {
+        const int s = __builtin_amdgcn_readfirstlane(bin_start[bin]);
+        const int e = __builtin_amdgcn_readfirstlane(bin_start[bin + 1]);
+        if (s == e) continue;
+        const int b0 = bin % nb0, b1 = (bin / nb0) % nb1, b2 = bin / (nb0 * nb1);
+        int ua = b0 - g.reach[0], ub = b0 + g.reach[0], ta0, ta1;
+        if (g.pbc[0]) {
+            ta0 = floordiv(ua, nb0);
+            ta1 = floordiv(ub, nb0);
+        } else {
+            ua = ua < 0 ? 0 : ua;
+            ub = ub >= nb0 ? nb0 - 1 : ub;
+            ta0 = ta1 = 0;
+        }
+        const int spr = ta1 - ta0 + 1;  // segments per stencil row
+        const int nseg = nrows * spr;
+        for (int a0 = s; a0 < e; a0 += WAVE) {
+            const int na = (e - a0) < WAVE ? (e - a0) : WAVE;
+            int np = 0, nc = 0;  // lane t counts the entries of atom a0 + t
+            for (int sb = 0; sb < nseg; sb += WAVE) {
+                // lane -> segment sb + lane: first sorted atom, length, image
                 int len = 0, jb = 0, img = 0;
-                if (ok) {
+                const int sg = sb + lane;
+                if (sg < nseg) {
+                    const int r = sg / spr, q = sg - r * spr;
+                    const int u1 = b1 + (r % n1r - g.reach[1]);
+                    const int u2 = b2 + (r / n1r - g.reach[2]);
+                    int t1 = 0, w1 = u1, t2 = 0, w2 = u2;
+                    bool ok = true;
+                    if (g.pbc[1]) { t1 = floordiv(u1, nb1); w1 = u1 - t1 * nb1; }
+                    else if (u1 < 0 || u1 >= nb1) ok = false;
+                    if (g.pbc[2]) { t2 = floordiv(u2, nb2); w2 = u2 - t2 * nb2; }
+                    else if (u2 < 0 || u2 >= nb2) ok = false;
                     const int t0 = ta0 + q;
                     const int lo = (ua > t0 * nb0 ? ua : t0 * nb0) - t0 * nb0;
                     const int hi = (ub < t0 * nb0 + nb0 - 1 ? ub : t0 * nb0 + nb0 - 1) - t0 * nb0;
-                    if (lo <= hi) {
+                    if (ok && lo <= hi) {
                         const int row = (w2 * nb1 + w1) * nb0;
                         jb = bin_start[row + lo];
                         len = bin_start[row + hi + 1] - jb;
                         img = ((t0 + g.timg[0]) * n1 + (t1 + g.timg[1])) * n2 + (t2 + g.timg[2]);
                     }
                 }
-                seg_jb[slot] = jb;
-                seg_img[slot] = img;
-                seg_off[slot] = len;
-            }
-        }
-        __syncthreads();
-        const int nseg = rcount * spr;
-        const int base = threadIdx.x * 4;
-        int l[4], tsum = 0;
+                const int incl = wave_incl_scan(len);
+                const int excl = incl - len;  // non-decreasing over the lanes
+                const int total = __builtin_amdgcn_readlane(incl, WAVE - 1);
+                for (int kb = 0; kb < total; kb += LIST_AHEAD * WAVE) {
+                    // candidates kb + u*64 + lane: sorted atom, image, position; each
+                    // lies in the last segment whose offset is <= its index
+                    int jj[LIST_AHEAD], ii[LIST_AHEAD];
+                    double4 pp[LIST_AHEAD];
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            l[q] = (base + q < nseg) ? seg_off[base + q] : 0;
-            tsum += l[q];
-        }
-        int total;
-        int ex = block_excl_scan(tsum, sh, &total);
+                    for (int u = 0; u < LIST_AHEAD; u++) {
+                        const int k = kb + u * WAVE + lane;
+                        int sl = 0;
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            if (base + q < nseg) seg_off[base + q] = ex;
-            ex += l[q];
-        }
-        __syncthreads();
-
-        for (int c0 = 0; c0 < total; c0 += LIST_TILE) {
-            const int tn = (total - c0) < LIST_TILE ? (total - c0) : LIST_TILE;
-            for (int t = threadIdx.x; t < tn; t += BLOCK) {
-                const int k = c0 + t;
-                int lo = 0, hi = nseg - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (seg_off[mid] <= k) lo = mid;
-                    else hi = mid - 1;
-                }
-                const int j = seg_jb[lo] + (k - seg_off[lo]);
-                const int img = seg_img[lo];
-                const double4 p = pos_s[j];
-                const double4 T = img_tab[img];
-                const uint32_t code = ((uint32_t)j << g.img_bits) | (uint32_t)img;
-                cand[t] = make_float4((float)(p.x + T.x - origin.x), (float)(p.y + T.y - origin.y),
-                                      (float)(p.z + T.z - origin.z), __int_as_float((int)code));
-            }
-            __syncthreads();
-            for (int a = s + wv; a < e; a += WAVES_PER_BLOCK) {
-                const double4 pa = pos_s[a];
-                const float ax = (float)(pa.x - origin.x), ay = (float)(pa.y - origin.y),
-                            az = (float)(pa.z - origin.z);
-                const uint32_t self_code = ((uint32_t)a << g.img_bits) | (uint32_t)img_self;
-                int np = first ? 0 : cnt_p[a];
-                int nc = first ? 0 : cnt_c[a];
-                uint32_t* lp = list_p + (size_t)a * cap_p;
-                uint32_t* lc = list_c + (size_t)a * cap_c;
-                for (int t0 = 0; t0 < tn; t0 += WAVE) {
-                    const int t = t0 + lane;
-                    bool inp = false, inc = false;
-                    uint32_t code = 0;
-                    if (t < tn) {
-                        const float4 q = cand[t];
-                        const float dx = q.x - ax, dy = q.y - ay, dz = q.z - az;
-                        const float r2 = dx * dx + dy * dy + dz * dz;
-                        code = (uint32_t)__float_as_int(q.w);
-                        const bool ok = code != self_code;
-                        inp = ok && r2 < rp2f;
-                        inc = ok && r2 < rc2f;
-                    }
-                    const unsigned long long bp = __ballot(inp);
-                    const unsigned long long bc = __ballot(inc);
-                    if (!count_only) {
-                        if (inp) {
-                            const int slot = np + __popcll(bp & lanemask);
-                            if (slot < cap_p) lp[slot] = code;
+                        for (int step = WAVE / 2; step >= 1; step >>= 1) {
+                            const int o = __shfl(excl, sl + step, WAVE);
+                            sl = (o <= k) ? sl + step : sl;
                         }
-                        if (inc) {
-                            const int slot = nc + __popcll(bc & lanemask);
-                            if (slot < cap_c) lc[slot] = code;
-                        }
+                        // all lanes take part in the shuffles (a lane cannot read an
+                        // inactive lane), then the lanes past the end are cleared
+                        const int o = __shfl(excl, sl, WAVE);
+                        const int jv = __shfl(jb, sl, WAVE) + (k - o);
+                        const int iv = __shfl(img, sl, WAVE);
+                        const bool in = k < total;
+                        jj[u] = in ? jv : 0;
+                        ii[u] = in ? iv : 0;
+                        pp[u] = pos_s[jj[u]];
                     }
-                    np += __popcll(bp);
-                    nc += __popcll(bc);
-                }
-                if (lane == 0) {
-                    cnt_p[a] = np;  // true count; readers clamp to the capacity
-                    cnt_c[a] = nc;
-                    if (!count_only && (np > cap_p || nc > cap_c)) atomicOr(status, ST_CAPACITY);
+                    const int nch = min(LIST_AHEAD, (total - kb + WAVE - 1) / WAVE);
+                    double qx[LIST_AHEAD], qy[LIST_AHEAD], qz[LIST_AHEAD];
+                    uint32_t code[LIST_AHEAD];
+                    bool valid[LIST_AHEAD];
+#pragma unroll
+                    for (int u = 0; u < LIST_AHEAD; u++) {
+                        valid[u] = kb + u * WAVE + lane < total;
+                        const double4 T = image<IMG>(s_img, img_tab, (uint32_t)ii[u]);
+                        qx[u] = pp[u].x + T.x;
+                        qy[u] = pp[u].y + T.y;
+                        qz[u] = pp[u].z + T.z;
+                        code[u] = ((uint32_t)jj[u] << g.img_bits) | (uint32_t)ii[u];
+                    }
+                    // the bin's atoms in turn, each against the block's candidates;
+                    // atom positions and entry counts are wave-uniform
+                    for (int t = 0; t < na; t++) {
+                        const int a = a0 + t;
+                        const double4 pa = pos_s[a];
+                        const uint32_t self = ((uint32_t)a << g.img_bits) | img_self;
+                        int np_t = __builtin_amdgcn_readlane(np, t);
+                        int nc_t = __builtin_amdgcn_readlane(nc, t);
+                        uint32_t* rowp = list_p + (size_t)a * cap_p;
+                        uint32_t* rowc = list_c + (size_t)a * cap_c;
+#pragma unroll
+                        for (int u = 0; u < LIST_AHEAD; u++) {
+                            if (u >= nch) break;
+                            const double dx = qx[u] - pa.x, dy = qy[u] - pa.y, dz = qz[u] - pa.z;
+                            const double r2 = dx * dx + dy * dy + dz * dz;
+                            const bool other = valid[u] & (code[u] != self);
+                            const bool inp = other & (r2 < rp2w);
+                            const bool inc = other & (r2 < rc2w);
+                            const unsigned long long bp = __ballot(inp);
+                            const unsigned long long bc = __ballot(inc);
+                            if constexpr (!COUNT) {
+                                if (inp) {
+                                    const int sp = np_t + lanes_below(bp);
+                                    if (sp < cap_p) rowp[(uint32_t)sp] = code[u];
+                                }
+                                if (inc) {
+                                    const int sc = nc_t + lanes_below(bc);
+                                    if (sc < cap_c) rowc[(uint32_t)sc] = code[u];
+                                }
+                            }
+                            np_t += (int)__popcll(bp);
+                            nc_t += (int)__popcll(bc);
+                        }
+                        const bool mine = lane == t;
+                        np = mine ? np_t : np;
+                        nc = mine ? nc_t : nc;
+                    }
                 }
             }
-            first = false;
-            __syncthreads();
-        }
-        if (total == 0 && first) {
-            // no candidate at all in this batch: counts still start at zero
-            for (int a = s + wv; a < e; a += WAVES_PER_BLOCK)
-                if (lane == 0) { cnt_p[a] = 0; cnt_c[a] = 0; }
-            first = false;
-            __syncthreads();
+            if (lane < na) {
+                cnt_p[a0 + lane] = np;  // true count; readers clamp to the capacity
+                cnt_c[a0 + lane] = nc;
+                if (!COUNT && (np > cap_p || nc > cap_c)) atomicOr(status, ST_CAPACITY);
+            }
         }
     }
 }
@@ -459,13 +479,13 @@ void launch_scatter(int n, const int* bin_of, const int* bin_start, int* fill,
 
 void launch_rank(int n, const int* perm_tmp, const int* bin_of, const int* bin_start,
                  const double* pos, const int32_t* type_copy, const double4* shift,
-                 int* perm, double4* pos_s, double4* shift_s, double4* ref_s,
-                 hipStream_t s)
+                 int* perm, double4* pos_s, double4* shift_s, double4* ref_s, int nbins,
+                 int* slab, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_rank, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s, n, perm_tmp,
                        bin_of, bin_start, pos, type_copy, shift, perm, pos_s, shift_s,
-                       ref_s);
+                       ref_s, nbins, slab);
 }
 
 void launch_update(int n, const double* pos, const int* perm,
@@ -478,15 +498,25 @@ void launch_update(int n, const double* pos, const int* perm,
                        pos, perm, shift_s, ref_s, pos_s, half_skin2, status);
 }
 
-void launch_list(int n, const double4* pos_s, const int* bin_start, const Geo& g,
+void launch_list(int n, const double4* pos_s, const int* bin_start, const int* slab, const Geo& g,
                  const double4* img_tab, double rp2, double rc2, uint32_t* list_p,
                  int* cnt_p, int cap_p, uint32_t* list_c, int* cnt_c, int cap_c,
                  int count_only, int* status, hipStream_t s)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_list, dim3(g.nbins), dim3(BLOCK), 0, s, pos_s, bin_start, g,
-                       img_tab, rp2, rc2, list_p, cnt_p, cap_p, list_c, cnt_c, cap_c,
-                       count_only, status);
+    const dim3 grid(split_blocks(g.nbins)), block(BLOCK);
+#define D3_LIST(I, C)                                                                          \
+    hipLaunchKernelGGL((k_list<I, C>), grid, block, 0, s, pos_s, bin_start, slab, g, img_tab, rp2, \
+                       rc2, list_p, cnt_p, cap_p, list_c, cnt_c, cap_c, status)
+    const bool lds = g.n_img <= IMG_LDS;
+    if (count_only) {
+        if (lds) D3_LIST(true, true);
+        else D3_LIST(false, true);
+    } else {
+        if (lds) D3_LIST(true, false);
+        else D3_LIST(false, false);
+    }
+#undef D3_LIST
 }
 
 void launch_cnt_stats(int n, const int* cnt_p, const int* cnt_c, int* out, hipStream_t s)

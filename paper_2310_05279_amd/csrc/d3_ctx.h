@@ -9,7 +9,7 @@
 
 namespace d3 {
 
-constexpr double BIN_DIV = 2.0;  // bins per list cutoff along each axis
+constexpr double BIN_DIV = 3.0;  // bins per list cutoff along each axis
 
 struct Buf {
     void* p = nullptr;
@@ -57,7 +57,7 @@ struct d3_ctx {
     bool built = false;
     bool fresh_build = false;
     // cell-sorted data
-    d3::Buf bin_of, shift, count, bin_start, scan_tmp, perm_tmp, perm;
+    d3::Buf bin_of, shift, count, bin_start, scan_tmp, perm_tmp, perm, slab;
     d3::Buf pos_s, shift_s, ref_s, type_copy, img_tab;
     // lists
     d3::Buf list_p, cnt_p, list_c, cnt_c;
@@ -83,7 +83,7 @@ struct d3_ctx {
     std::vector<d3::Buf*> all_buffers()
     {
         return {&d_tab, &d_c6, &d_pc, &bin_of, &shift, &count, &bin_start,
-                &scan_tmp, &perm_tmp, &perm, &pos_s, &shift_s, &ref_s, &type_copy,
+                &scan_tmp, &perm_tmp, &perm, &slab, &pos_s, &shift_s, &ref_s, &type_copy,
                 &img_tab, &list_p, &cnt_p, &list_c, &cnt_c, &cn, &cnf, &w, &wd, &P,
                 &Pf, &G, &Fp, &U, &vpart, &vpart2, &status, &maxcnt, &ticket, &md_scratch};
     }
