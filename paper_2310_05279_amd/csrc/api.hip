@@ -256,7 +256,11 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
     const Geo& g = c->geo;
     int* count = c->count.as<int>();
     int* fill = count + g.nbins;
-    HIPCHK(hipMemsetAsync(count, 0, 2 * (size_t)g.nbins * sizeof(int), s));
+    // the bin counts and scatter cursors are left at zero by the scan of the
+    // previous build; they are cleared here only after an allocation or a
+    // build that did not complete
+    if (!c->counts_clean) HIPCHK(hipMemsetAsync(count, 0, 2 * (size_t)g.nbins * sizeof(int), s));
+    c->counts_clean = false;
     launch_bin(n, pos, type, c->n_elem, g, c->bin_of.as<int>(), c->shift.as<double4>(), count,
                c->type_copy.as<int32_t>(), c->status.as<int>(), s);
     launch_scan(g.nbins, count, c->bin_start.as<int>(), c->scan_tmp.as<int>(), s);
@@ -289,6 +293,7 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
                 rp * rp, rcn * rcn, c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p,
                 c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, 0, c->status.as<int>(), s);
     HIPCHK(hipGetLastError());
+    c->counts_clean = true;
     return D3_OK;
 }
 
@@ -324,6 +329,7 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
         std::memcpy(c->cell, cell, sizeof(c->cell));
         D3CHK(alloc_atoms(c, n));
         D3CHK(ensure(c->count, 2 * (size_t)g.nbins * sizeof(int)));
+        c->counts_clean = false;
         D3CHK(ensure(c->bin_start, ((size_t)g.nbins + 1) * sizeof(int)));
         D3CHK(ensure(c->slab, 16 * sizeof(int)));
         D3CHK(ensure(c->scan_tmp, ((size_t)g.nbins / 1024 + 4) * sizeof(int)));

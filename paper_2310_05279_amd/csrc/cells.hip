@@ -85,33 +85,58 @@ __device__ int block_excl_scan(int v, int* sh, int* total)
     return incl - v;
 }
 
-// exclusive scan of the bin counts; one workgroup of 1024 threads, each
-// owning a contiguous chunk of bins
+// Exclusive scan of the bin counts by one workgroup of 1024 threads, in
+// tiles of 4096 bins (4 consecutive bins per thread, wave scans through
+// shuffles, the 16 wave totals through LDS).  The counts and the scatter
+// cursors (count[m .. 2m)) are cleared as they are consumed, so the next
+// build starts from zero without a memset.
 __global__ void __launch_bounds__(1024)
-k_scan_one(int m, const int* __restrict__ in, int* __restrict__ out)
+k_scan_one(int m, int* __restrict__ count, int* __restrict__ out)
 {
-    __shared__ int sh[1024];
-    const int per = (m + 1023) / 1024;
-    const int a = threadIdx.x * per;
-    const int b = min(a + per, m);
-    int sum = 0;
-    for (int k = a; k < b; k++) sum += in[k];
-    int total;
-    int ex = block_excl_scan(sum, sh, &total);
-    for (int k = a; k < b; k++) {
-        const int v = in[k];
-        out[k] = ex;
-        ex += v;
+    __shared__ int wsum[1024 / WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    int carry = 0;
+    for (int base = 0; base < m; base += 4096) {
+        const int k0 = base + 4 * threadIdx.x;
+        int v[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) v[q] = (k0 + q < m) ? count[k0 + q] : 0;
+        const int tsum = v[0] + v[1] + v[2] + v[3];
+        int incl = tsum;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const int t = __shfl_up(incl, d, WAVE);
+            if (lane >= d) incl += t;
+        }
+        if (lane == WAVE - 1) wsum[wv] = incl;
+        __syncthreads();
+        int before = carry, tile = 0;
+        for (int w = 0; w < 1024 / WAVE; w++) {
+            const int ws = wsum[w];
+            before += (w < wv) ? ws : 0;
+            tile += ws;
+        }
+        int ex = before + incl - tsum;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            if (k0 + q < m) {
+                out[k0 + q] = ex;
+                count[k0 + q] = 0;
+                count[m + k0 + q] = 0;
+            }
+            ex += v[q];
+        }
+        carry += tile;
+        __syncthreads();
     }
-    if (threadIdx.x == 0) out[m] = total;
+    if (threadIdx.x == 0) out[m] = carry;
 }
 
 // three-phase exclusive scan for large bin tables, 1024 bins per block
 constexpr int SCAN_PER_BLOCK = 1024;
 
 __global__ void __launch_bounds__(BLOCK)
-k_scan_local(int m, const int* __restrict__ in, int* __restrict__ out,
-             int* __restrict__ blocksum)
+k_scan_local(int m, int* __restrict__ in, int* __restrict__ out, int* __restrict__ blocksum)
 {
     __shared__ int sh[BLOCK];
     int base = blockIdx.x * SCAN_PER_BLOCK + threadIdx.x * 4;
@@ -125,7 +150,11 @@ k_scan_local(int m, const int* __restrict__ in, int* __restrict__ out,
     int excl = block_excl_scan(s, sh, &total);
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        if (base + q < m) out[base + q] = excl;
+        if (base + q < m) {
+            out[base + q] = excl;
+            in[base + q] = 0;  // counts and scatter cursors start at zero next build
+            in[m + base + q] = 0;
+        }
         excl += v[q];
     }
     if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
@@ -454,10 +483,9 @@ void launch_bin(int n, const double* pos, const int32_t* type, int n_elem,
                        type, n_elem, g, bin_of, shift, count, type_copy, status);
 }
 
-void launch_scan(int nbins, const int* count, int* bin_start, int* tmp,
-                 hipStream_t s)
+void launch_scan(int nbins, int* count, int* bin_start, int* tmp, hipStream_t s)
 {
-    if (nbins <= 1024 * 256) {
+    if (nbins <= 65536) {
         hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, s, nbins, count, bin_start);
         return;
     }

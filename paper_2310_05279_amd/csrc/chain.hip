@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(1024)
 k_final(int nparts, const double* __restrict__ part_a, const double* __restrict__ part_b,
         double* __restrict__ energy, double* __restrict__ virial, int accumulate)
 {
-    __shared__ double fin[7][1024];
+    __shared__ double fin[1024 / WAVE][8];
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nparts; b += 1024) {
         const double4* pa = (const double4*)(part_a + (size_t)b * 8);
@@ -131,19 +131,23 @@ k_final(int nparts, const double* __restrict__ part_a, const double* __restrict_
         acc[5] += a1.y + c1.y;
         acc[6] += a1.z + c1.z;
     }
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
 #pragma unroll
-    for (int c = 0; c < 7; c++) fin[c][threadIdx.x] = acc[c];
-    __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off)
-#pragma unroll
-            for (int c = 0; c < 7; c++) fin[c][threadIdx.x] += fin[c][threadIdx.x + off];
-        __syncthreads();
+    for (int c = 0; c < 7; c++) {
+        const double t = wave_sum(acc[c]);
+        if (lane == 0) fin[wv][c] = t;
     }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        double t = 0.0;
+        for (int w = 0; w < 1024 / WAVE; w++) t += fin[w][threadIdx.x];
+        fin[0][threadIdx.x] = t;  // wave 0 is the only reader below
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const double e = fin[0][0];
-        const double v[9] = {fin[1][0], fin[2][0], fin[3][0], fin[2][0], fin[4][0],
-                             fin[5][0], fin[3][0], fin[5][0], fin[6][0]};
+        const double* f = fin[0];
+        const double e = f[0];
+        const double v[9] = {f[1], f[2], f[3], f[2], f[4], f[5], f[3], f[5], f[6]};
         if (accumulate) {
             energy[0] += e;
             if (virial)

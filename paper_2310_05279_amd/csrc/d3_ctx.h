@@ -56,6 +56,7 @@ struct d3_ctx {
     d3::Geo geo{};
     bool built = false;
     bool fresh_build = false;
+    bool counts_clean = false;  // bin counts and scatter cursors are zero
     // cell-sorted data
     d3::Buf bin_of, shift, count, bin_start, scan_tmp, perm_tmp, perm, slab;
     d3::Buf pos_s, shift_s, ref_s, type_copy, img_tab;

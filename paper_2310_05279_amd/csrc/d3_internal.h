@@ -51,8 +51,7 @@ struct PairScal {
 void launch_bin(int n, const double* pos, const int32_t* type, int n_elem,
                 const Geo& g, int* bin_of, double4* shift, int* count,
                 int32_t* type_copy, int* status, hipStream_t s);
-void launch_scan(int nbins, const int* count, int* bin_start, int* tmp,
-                 hipStream_t s);
+void launch_scan(int nbins, int* count, int* bin_start, int* tmp, hipStream_t s);
 void launch_scatter(int n, const int* bin_of, const int* bin_start, int* fill,
                     int* perm_tmp, hipStream_t s);
 void launch_rank(int n, const int* perm_tmp, const int* bin_of, const int* bin_start,
