@@ -82,9 +82,13 @@ k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ im
                 virial_add(vir, -0.5 * coef, dx, dy, dz);
             }
         }
-        fx = wave_sum(fx);
-        fy = wave_sum(fy);
-        fz = wave_sum(fz);
+        {
+            double t[3] = {fx, fy, fz};
+            wave_sums(t);
+            fx = t[0];
+            fy = t[1];
+            fz = t[2];
+        }
         if (lane == 0) {
             const size_t o = (size_t)perm[i];
             const double f0 = Fp[3 * (size_t)i] + fx;
@@ -132,11 +136,10 @@ k_final(int nparts, const double* __restrict__ part_a, const double* __restrict_
         acc[6] += a1.z + c1.z;
     }
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    wave_sums(acc);
+    if (lane == 0)
 #pragma unroll
-    for (int c = 0; c < 7; c++) {
-        const double t = wave_sum(acc[c]);
-        if (lane == 0) fin[wv][c] = t;
-    }
+        for (int c = 0; c < 7; c++) fin[wv][c] = acc[c];
     __syncthreads();
     if (threadIdx.x < 7) {
         double t = 0.0;

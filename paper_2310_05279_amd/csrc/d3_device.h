@@ -14,45 +14,66 @@ constexpr int DPP_ROW_ROR8 = 0x128;  // row_ror:8
 constexpr int DPP_ROW_BCAST15 = 0x142;
 constexpr int DPP_ROW_BCAST31 = 0x143;
 
+// v from the lane the DPP control selects; lanes the row mask excludes get
+// an undefined value (the sums below only read lane 63, whose inputs are
+// always selected)
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_f64(double v)
 {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xF, false);
-    const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xF, false);
-    return __hiloint2double(hi2, lo2);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes of a wave; the result is wave-uniform.  Row sums
-// with quad permutes and row rotations, then row broadcasts 15 and 31
-// carry the partial sums into lane 63, which is read back.
+// Sums over the 64 lanes of a wave of N values at once; the results are
+// wave-uniform.  Every lane of a row gets the row sum from quad permutes
+// and row rotations, then row broadcasts 15 and 31 carry the partial sums
+// into lane 63, which is read back.  The N values go through each step
+// together, so their DPP wait states overlap.
+template <int N>
+__device__ __forceinline__ void wave_sums(double (&v)[N])
+{
+#pragma unroll
+    for (int c = 0; c < N; c++) v[c] += dpp_f64<DPP_QUAD_1032, 0xF>(v[c]);
+#pragma unroll
+    for (int c = 0; c < N; c++) v[c] += dpp_f64<DPP_QUAD_2301, 0xF>(v[c]);
+#pragma unroll
+    for (int c = 0; c < N; c++) v[c] += dpp_f64<DPP_ROW_ROR4, 0xF>(v[c]);
+#pragma unroll
+    for (int c = 0; c < N; c++) v[c] += dpp_f64<DPP_ROW_ROR8, 0xF>(v[c]);
+#pragma unroll
+    for (int c = 0; c < N; c++) v[c] += dpp_f64<DPP_ROW_BCAST15, 0xA>(v[c]);
+#pragma unroll
+    for (int c = 0; c < N; c++) v[c] += dpp_f64<DPP_ROW_BCAST31, 0xC>(v[c]);
+#pragma unroll
+    for (int c = 0; c < N; c++) {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v[c]), 63);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v[c]), 63);
+        v[c] = __hiloint2double(hi, lo);
+    }
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
-    v += dpp_f64<DPP_QUAD_1032, 0xF>(v);
-    v += dpp_f64<DPP_QUAD_2301, 0xF>(v);
-    v += dpp_f64<DPP_ROW_ROR4, 0xF>(v);
-    v += dpp_f64<DPP_ROW_ROR8, 0xF>(v);
-    v += dpp_f64<DPP_ROW_BCAST15, 0xA>(v);
-    v += dpp_f64<DPP_ROW_BCAST31, 0xC>(v);
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-    return __hiloint2double(hi, lo);
+    double a[1] = {v};
+    wave_sums(a);
+    return a[0];
 }
 
 __device__ __forceinline__ float wave_sum(float v)
 {
     int b = __float_as_int(v);
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, b, DPP_QUAD_1032, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(b, DPP_QUAD_1032, 0xF, 0xF, false));
     b = __float_as_int(v);
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, b, DPP_QUAD_2301, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(b, DPP_QUAD_2301, 0xF, 0xF, false));
     b = __float_as_int(v);
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, b, DPP_ROW_ROR4, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(b, DPP_ROW_ROR4, 0xF, 0xF, false));
     b = __float_as_int(v);
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, b, DPP_ROW_ROR8, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(b, DPP_ROW_ROR8, 0xF, 0xF, false));
     b = __float_as_int(v);
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, b, DPP_ROW_BCAST15, 0xA, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(b, DPP_ROW_BCAST15, 0xA, 0xF, false));
     b = __float_as_int(v);
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, b, DPP_ROW_BCAST31, 0xC, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(b, DPP_ROW_BCAST31, 0xC, 0xF, false));
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
@@ -130,11 +151,13 @@ __device__ __forceinline__ void block_partials(const double* vals, double* __res
 {
     __shared__ double red[WAVES_PER_BLOCK][8];
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    double t[7];
 #pragma unroll
-    for (int c = 0; c < 7; c++) {
-        const double v = wave_sum(vals[c]);
-        if (lane == 0) red[wv][c] = v;
-    }
+    for (int c = 0; c < 7; c++) t[c] = vals[c];
+    wave_sums(t);
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < 7; c++) red[wv][c] = t[c];
     __syncthreads();
     if (threadIdx.x < 7) {
         double t = 0.0;

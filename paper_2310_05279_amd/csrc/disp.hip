@@ -29,6 +29,19 @@ namespace d3 {
 
 constexpr int M_LDS_ELEM = 8;  // C6 reference table staged in LDS up to 8 elements
 
+// 1/x for the positive, normal denominators of Eq. 2 (r^6 + Rd^6 times
+// r^8 + Rd^8): the hardware estimate refined by two Newton-Raphson steps
+// y <- y + y (1 - x y), each written with fused multiply-adds; the result
+// is within an ulp of 1/x.
+__device__ __forceinline__ double recip(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
 template <bool F32>
 struct Nbr;
 template <>
@@ -157,7 +170,7 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
                 dc6 = in ? dc6 : 0.0;
                 const double r4 = r2 * r2, r6 = r4 * r2, r8 = r4 * r4;
                 const double A = r6 + c.x, B = r8 + c.y;
-                const double inv = 1.0 / (A * B);
+                const double inv = recip(A * B);
                 const double t6 = B * inv, t8 = A * inv;
                 const double a6 = sc.s6 * t6, a8 = c.w * t8;
                 const double gg = a6 + a8;  // -dphi/dC6
@@ -203,11 +216,15 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
             code_n = code_nn;
             nb_c = nb_n;
         }
-        fx = wave_sum(fx);
-        fy = wave_sum(fy);
-        fz = wave_sum(fz);
-        ue = wave_sum(ue);
-        g = wave_sum(g);
+        {
+            double t[5] = {fx, fy, fz, ue, g};
+            wave_sums(t);
+            fx = t[0];
+            fy = t[1];
+            fz = t[2];
+            ue = t[3];
+            g = t[4];
+        }
         esum += ue;
         if (lane == 0) {
             Fp[3 * (size_t)i] = fx;

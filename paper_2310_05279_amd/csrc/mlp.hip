@@ -737,11 +737,15 @@ k_pair_sur(int n, const double4* __restrict__ pos_s, const double4* __restrict__
             }
             __builtin_amdgcn_wave_barrier();  // LDS rows are reused by the next chunk
         }
-        fx = wave_sum(fx);
-        fy = wave_sum(fy);
-        fz = wave_sum(fz);
-        ue = wave_sum(ue);
-        g = wave_sum(g);
+        {
+            double t[5] = {fx, fy, fz, ue, g};
+            wave_sums(t);
+            fx = t[0];
+            fy = t[1];
+            fz = t[2];
+            ue = t[3];
+            g = t[4];
+        }
         esum += ue;
         if (lane == 0) {
             Fp[3 * (size_t)i] = fx;
