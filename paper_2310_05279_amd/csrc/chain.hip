@@ -9,6 +9,10 @@
 
 namespace d3 {
 
+constexpr int ROW = 16;  // lanes per atom: four atoms per wave, one per DPP row
+
+static int chain_blocks(int n) { return split_blocks((n + WAVE / ROW - 1) / (WAVE / ROW)); }
+
 template <bool F32, bool IMG>
 __global__ void __launch_bounds__(BLOCK)
 k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_tab, int n_img,
@@ -24,19 +28,27 @@ k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ im
     if (threadIdx.x < MAXELEM) s_rcov[threadIdx.x] = tab->rcov[threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
+    const int rl = lane & (ROW - 1);  // lane within the row
     const uint32_t img_mask = (1u << img_bits) - 1u;
     double vir[6] = {0, 0, 0, 0, 0, 0};
-    const Walk wk = atom_walk(n);
-    for (int i = wk.first; i < wk.end; i += wk.step) {
+    const int ngroups = (n + WAVE / ROW - 1) / (WAVE / ROW);
+    const Walk wk = atom_walk(ngroups);
+    for (int gi_ = wk.first; gi_ < wk.end; gi_ += wk.step) {
+        const int i0 = gi_ * (WAVE / ROW) + lane / ROW;
+        const bool live = i0 < n;
+        const int i = live ? i0 : n - 1;
         const double4 pi = pos_s[i];
-        const int zi = __builtin_amdgcn_readfirstlane(zbits(pi.w));
+        const int zi = zbits(pi.w);
         const double rci = s_rcov[zi];
         const double gi = G[i];
-        const int cnt = min(cnt_c[i], cap_c);
+        const int cnt = live ? min(cnt_c[i], cap_c) : 0;
         const uint32_t* lc = list_c + (size_t)i * cap_c;
+        // steps: the longest of the four lists
+        int mc = max(cnt, __shfl_xor(cnt, ROW, WAVE));
+        mc = __builtin_amdgcn_readfirstlane(max(mc, __shfl_xor(mc, 2 * ROW, WAVE)));
         double fx = 0.0, fy = 0.0, fz = 0.0;
-        for (int k0 = 0; k0 < cnt; k0 += WAVE) {
-            const int k = k0 + lane;
+        for (int k0 = 0; k0 < mc; k0 += ROW) {
+            const int k = k0 + rl;
             const uint32_t code = list_code(lc, k, cnt, cap_c);
             const uint32_t j = code >> img_bits;
             const double4 pj = pos_s[j];
@@ -82,14 +94,10 @@ k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ im
                 virial_add(vir, -0.5 * coef, dx, dy, dz);
             }
         }
-        {
-            double t[3] = {fx, fy, fz};
-            wave_sums(t);
-            fx = t[0];
-            fy = t[1];
-            fz = t[2];
-        }
-        if (lane == 0) {
+        fx = row_sum(fx);
+        fy = row_sum(fy);
+        fz = row_sum(fz);
+        if (live && rl == 0) {
             const size_t o = (size_t)perm[i];
             const double f0 = Fp[3 * (size_t)i] + fx;
             const double f1 = Fp[3 * (size_t)i + 1] + fy;
@@ -118,15 +126,18 @@ k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ im
 // Energy (Eq. 1) and virial from the workgroup partials of both passes,
 // summed in a fixed order by one workgroup.
 __global__ void __launch_bounds__(1024)
-k_final(int nparts, const double* __restrict__ part_a, const double* __restrict__ part_b,
+k_final(int na, const double* __restrict__ part_a, int nb, const double* __restrict__ part_b,
         double* __restrict__ energy, double* __restrict__ virial, int accumulate)
 {
     __shared__ double fin[1024 / WAVE][8];
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nparts; b += 1024) {
+    const int nmax = na > nb ? na : nb;
+    for (int b = threadIdx.x; b < nmax; b += 1024) {
+        const double4 z = make_double4(0.0, 0.0, 0.0, 0.0);
         const double4* pa = (const double4*)(part_a + (size_t)b * 8);
         const double4* pb = (const double4*)(part_b + (size_t)b * 8);
-        const double4 a0 = pa[0], a1 = pa[1], c0 = pb[0], c1 = pb[1];
+        const double4 a0 = b < na ? pa[0] : z, a1 = b < na ? pa[1] : z;
+        const double4 c0 = b < nb ? pb[0] : z, c1 = b < nb ? pb[1] : z;
         acc[0] += a0.x + c0.x;
         acc[1] += a0.y + c0.y;
         acc[2] += a0.z + c0.z;
@@ -178,7 +189,7 @@ void launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab,
                   int accumulate, double* part, hipStream_t s)
 {
     if (n <= 0) return;
-    const dim3 grid(split_blocks(n)), block(BLOCK);
+    const dim3 grid(chain_blocks(n)), block(BLOCK);
     const bool lds = n_img <= IMG_LDS;
 #define D3_CHAIN(F, I)                                                                          \
     hipLaunchKernelGGL((k_chain<F, I>), grid, block, 0, s, n, pos_s, img_tab, n_img, img_bits,  \
@@ -197,7 +208,7 @@ void launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab,
 void launch_final(int n, const double* part_a, const double* part_b, double* energy,
                   double* virial, int accumulate, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, s, split_blocks(n), part_a, part_b,
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, s, split_blocks(n), part_a, chain_blocks(n), part_b,
                        energy, virial, accumulate);
 }
 

@@ -1,16 +1,18 @@
 // Coordination numbers (Eq. 4) and the normalised Gaussian weights of
 // Eq. 3 for every atom.
 //
-// One wavefront treats one atom at a time: its lanes walk the atom's
-// R_cn list (one 64-entry chunk covers a typical list), the counting
-// function is summed with a DPP wave reduction, and the weights
+// One wavefront treats four atoms at a time, one per DPP row of 16 lanes:
+// a row walks its atom's R_cn list 16 entries per step and sums the
+// counting function with a row reduction.  The weights
 // w_a = L_a / sum_b L_b, L_a = exp(-4 (n - n_ref,a)^2 + shift), with the
 // largest exponent shifted to zero (an exact identity that keeps the sums
-// representable), and their CN derivatives w'_a are formed in FP64 in
-// every mode.
+// representable), and their CN derivatives w'_a are then formed by the
+// row's first K lanes, one reference each, in FP64 in every mode.
 #include "d3_device.h"
 
 namespace d3 {
+
+constexpr int ROW = 16;  // lanes per atom
 
 template <bool F32, bool IMG>
 __global__ void __launch_bounds__(BLOCK)
@@ -21,21 +23,35 @@ k_cn(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_t
 {
     __shared__ double4 s_img[IMG ? IMG_LDS : 1];
     __shared__ double s_rcov[MAXELEM];
+    __shared__ double s_cnref[MAXELEM * MAXREF];
+    __shared__ int s_nref[MAXELEM];
     load_images<IMG>(s_img, img_tab, n_img);
-    if (threadIdx.x < MAXELEM) s_rcov[threadIdx.x] = tab->rcov[threadIdx.x];
+    if (threadIdx.x < MAXELEM) {
+        s_rcov[threadIdx.x] = tab->rcov[threadIdx.x];
+        s_nref[threadIdx.x] = tab->n_ref[threadIdx.x];
+    }
+    if (threadIdx.x < MAXELEM * MAXREF) s_cnref[threadIdx.x] = tab->cn_ref[threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & (WAVE - 1);
+    const int rl = lane & (ROW - 1);  // lane within the row
     const uint32_t img_mask = (1u << img_bits) - 1u;
-    const Walk wk = atom_walk(n);
-    for (int i = wk.first; i < wk.end; i += wk.step) {
-        const double4 pi = pos_s[i];
-        const int zi = __builtin_amdgcn_readfirstlane(zbits(pi.w));
+    const int ngroups = (n + WAVE / ROW - 1) / (WAVE / ROW);
+    const Walk wk = atom_walk(ngroups);
+    for (int gi = wk.first; gi < wk.end; gi += wk.step) {
+        const int i = gi * (WAVE / ROW) + lane / ROW;
+        const bool live = i < n;
+        const int ic = live ? i : n - 1;
+        const double4 pi = pos_s[ic];
+        const int zi = zbits(pi.w);
         const double rci = s_rcov[zi];
-        const int cnt = min(cnt_c[i], cap_c);
-        const uint32_t* lc = list_c + (size_t)i * cap_c;
+        const int cnt = live ? min(cnt_c[ic], cap_c) : 0;
+        const uint32_t* lc = list_c + (size_t)ic * cap_c;
+        // steps: the longest of the four lists
+        int mc = max(cnt, __shfl_xor(cnt, ROW, WAVE));
+        mc = __builtin_amdgcn_readfirstlane(max(mc, __shfl_xor(mc, 2 * ROW, WAVE)));
         double sum = 0.0;
-        for (int k0 = 0; k0 < cnt; k0 += WAVE) {
-            const int k = k0 + lane;
+        for (int k0 = 0; k0 < mc; k0 += ROW) {
+            const int k = k0 + rl;
             const uint32_t code = list_code(lc, k, cnt, cap_c);
             const double4 pj = pos_s[code >> img_bits];
             const double4 T = image<IMG>(s_img, img_tab, code & img_mask);
@@ -57,47 +73,27 @@ k_cn(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_t
             }
             sum += in ? f : 0.0;
         }
-        const double ni = wave_sum(sum);
-        // Gaussian weights of Eq. 3 for atom i, normalised after shifting
-        // every exponent by the largest one (FP64 in every mode)
-        const int K = tab->n_ref[zi];
-        double dl[MAXREF], wl[MAXREF], wdl[MAXREF];
-        double m = 1e300;
-#pragma unroll
-        for (int a = 0; a < MAXREF; a++) {
-            dl[a] = ni - tab->cn_ref[zi * MAXREF + a];
-            if (a < K) m = fmin(m, dl[a] * dl[a]);
-        }
-        double z = 0.0;
-#pragma unroll
-        for (int a = 0; a < MAXREF; a++) {
-            wl[a] = (a < K) ? exp(-4.0 * (dl[a] * dl[a] - m)) : 0.0;
-            z += wl[a];
-        }
-        const double iz = 1.0 / z;
-        double s = 0.0;
-#pragma unroll
-        for (int a = 0; a < MAXREF; a++) {
-            wl[a] *= iz;
-            s += wl[a] * dl[a];
-        }
-#pragma unroll
-        for (int a = 0; a < MAXREF; a++) wdl[a] = (a < K) ? -8.0 * wl[a] * (dl[a] - s) : 0.0;
-        if (lane == 0) cn[i] = ni;
-        if (lane < 8) {
-            double wv = 0.0, wdv = 0.0;
-#pragma unroll
-            for (int a = 0; a < MAXREF; a++)
-                if (lane == a) {
-                    wv = wl[a];
-                    wdv = wdl[a];
-                }
-            if (lane < MAXREF) {
-                w[(size_t)i * MAXREF + lane] = wv;
-                wd[(size_t)i * MAXREF + lane] = wdv;
+        const double ni = row_first(row_sum(sum));
+        // Gaussian weights of Eq. 3: lane a < K of the row takes reference a
+        const int K = s_nref[zi];
+        const bool ref = rl < K;
+        const double dl = ni - s_cnref[zi * MAXREF + (rl < MAXREF ? rl : MAXREF - 1)];
+        const double m = row_min(ref ? dl * dl : 1e300);
+        const double L = ref ? exp(-4.0 * (dl * dl - m)) : 0.0;
+        const double wl = L / row_first(row_sum(L));
+        const double s = row_first(row_sum(wl * dl));
+        const double wdl = ref ? -8.0 * wl * (dl - s) : 0.0;
+        if (live) {
+            if (rl == 0) cn[i] = ni;
+            if (rl < MAXREF) {
+                w[(size_t)i * MAXREF + rl] = wl;
+                wd[(size_t)i * MAXREF + rl] = wdl;
             }
-            if (F32) Wf[(size_t)i * WROWF + lane] = (float)wv;
-            else if (lane < WROW) W[(size_t)i * WROW + lane] = wv;
+            if (F32) {
+                if (rl < WROWF) Wf[(size_t)i * WROWF + rl] = (float)wl;
+            } else if (rl < WROW) {
+                W[(size_t)i * WROW + rl] = wl;
+            }
         }
     }
 }
@@ -108,7 +104,7 @@ void launch_cn(int mode, int n, const double4* pos_s, const double4* img_tab, in
                float* Wf, hipStream_t s)
 {
     if (n <= 0) return;
-    const dim3 grid(split_blocks(n)), block(BLOCK);
+    const dim3 grid(split_blocks((n + WAVE / ROW - 1) / (WAVE / ROW))), block(BLOCK);
     const bool lds = n_img <= IMG_LDS;
 #define D3_CN(F, I)                                                                          \
     hipLaunchKernelGGL((k_cn<F, I>), grid, block, 0, s, n, pos_s, img_tab, n_img, img_bits,  \

@@ -53,6 +53,27 @@ __device__ __forceinline__ void wave_sums(double (&v)[N])
     }
 }
 
+// Sum over each DPP row (16 lanes): quad permutes then row rotations by 4
+// and 8.  Every lane of a row ends with the row sum, added in a lane-
+// dependent order; callers that need one value per row broadcast a lane.
+__device__ __forceinline__ double row_sum(double v)
+{
+    v += dpp_f64<DPP_QUAD_1032, 0xF>(v);
+    v += dpp_f64<DPP_QUAD_2301, 0xF>(v);
+    v += dpp_f64<DPP_ROW_ROR4, 0xF>(v);
+    v += dpp_f64<DPP_ROW_ROR8, 0xF>(v);
+    return v;
+}
+
+__device__ __forceinline__ double row_min(double v)
+{
+    v = fmin(v, dpp_f64<DPP_QUAD_1032, 0xF>(v));
+    v = fmin(v, dpp_f64<DPP_QUAD_2301, 0xF>(v));
+    v = fmin(v, dpp_f64<DPP_ROW_ROR4, 0xF>(v));
+    v = fmin(v, dpp_f64<DPP_ROW_ROR8, 0xF>(v));
+    return v;
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
     double a[1] = {v};
@@ -88,6 +109,15 @@ constexpr int WROW = 6;        // doubles per FP64 weight row (5 + pad)
 constexpr int WROWF = 8;       // floats per FP32 weight row (5 + pad)
 
 __device__ __forceinline__ int zbits(double w) { return __double2loint(w); }
+
+// the value of the first lane of this lane's row
+__device__ __forceinline__ double row_first(double v)
+{
+    const int src = (int)(threadIdx.x & (WAVE - 16));
+    const int lo = __shfl(__double2loint(v), src, WAVE);
+    const int hi = __shfl(__double2hiint(v), src, WAVE);
+    return __hiloint2double(hi, lo);
+}
 
 // logical workgroup index: logical blocks [x G/8, (x+1) G/8) run on XCD x
 // (workgroups are dispatched round-robin over the 8 XCDs)
