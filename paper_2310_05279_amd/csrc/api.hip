@@ -256,9 +256,9 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
     const Geo& g = c->geo;
     int* count = c->count.as<int>();
     int* fill = count + g.nbins;
-    // the bin counts and scatter cursors are left at zero by the scan of the
-    // previous build; they are cleared here only after an allocation or a
-    // build that did not complete
+    // the bin counts and scatter cursors are left at zero by the ranking
+    // kernel of the previous build; they are cleared here only after an
+    // allocation or a build that did not complete
     if (!c->counts_clean) HIPCHK(hipMemsetAsync(count, 0, 2 * (size_t)g.nbins * sizeof(int), s));
     c->counts_clean = false;
     launch_bin(n, pos, type, c->n_elem, g, c->bin_of.as<int>(), c->shift.as<double4>(), count,
@@ -268,7 +268,7 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
     launch_rank(n, c->perm_tmp.as<int>(), c->bin_of.as<int>(), c->bin_start.as<int>(), pos,
                 c->type_copy.as<int32_t>(), c->shift.as<double4>(), c->perm.as<int>(),
                 c->pos_s.as<double4>(), c->shift_s.as<double4>(), c->ref_s.as<double4>(),
-                g.nbins, c->slab.as<int>(), s);
+                g.nbins, c->slab.as<int>(), count, s);
     HIPCHK(hipGetLastError());
     const double rp = c->prm.r_pot + c->prm.skin, rcn = c->prm.r_cn + c->prm.skin;
     if (size_lists) {

@@ -85,49 +85,57 @@ __device__ int block_excl_scan(int v, int* sh, int* total)
     return incl - v;
 }
 
-// Exclusive scan of the bin counts by one workgroup of 1024 threads, in
-// tiles of 4096 bins (4 consecutive bins per thread, wave scans through
-// shuffles, the 16 wave totals through LDS).  The counts and the scatter
-// cursors (count[m .. 2m)) are cleared as they are consumed, so the next
-// build starts from zero without a memset.
+// Exclusive scan of up to SCAN_ONE_MAX bin counts by one workgroup of 1024
+// threads, in tiles of 4096 bins: each thread takes 4 consecutive bins (the
+// next tile's are loaded while this one is scanned), the thread sums are
+// scanned across the wave with shuffles and across the 16 waves through LDS.
+constexpr int SCAN_ONE_MAX = 65536;
+
 __global__ void __launch_bounds__(1024)
-k_scan_one(int m, int* __restrict__ count, int* __restrict__ out)
+k_scan_one(int m, const int* __restrict__ count, int* __restrict__ out)
 {
-    __shared__ int wsum[1024 / WAVE];
+    __shared__ int wsum[2][1024 / WAVE];
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     int carry = 0;
-    for (int base = 0; base < m; base += 4096) {
+    int4 vn;
+    {
+        const int k0 = 4 * threadIdx.x;
+        vn = (k0 + 3 < m) ? *(const int4*)(count + k0)
+                          : make_int4(k0 < m ? count[k0] : 0, k0 + 1 < m ? count[k0 + 1] : 0,
+                                      k0 + 2 < m ? count[k0 + 2] : 0, 0);
+    }
+    for (int base = 0, t = 0; base < m; base += 4096, t ^= 1) {
         const int k0 = base + 4 * threadIdx.x;
-        int v[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++) v[q] = (k0 + q < m) ? count[k0 + q] : 0;
-        const int tsum = v[0] + v[1] + v[2] + v[3];
+        const int4 v = vn;
+        const int kn = k0 + 4096;
+        if (base + 4096 < m)
+            vn = (kn + 3 < m) ? *(const int4*)(count + kn)
+                              : make_int4(kn < m ? count[kn] : 0, kn + 1 < m ? count[kn + 1] : 0,
+                                          kn + 2 < m ? count[kn + 2] : 0, 0);
+        const int tsum = v.x + v.y + v.z + v.w;
         int incl = tsum;
 #pragma unroll
         for (int d = 1; d < WAVE; d <<= 1) {
-            const int t = __shfl_up(incl, d, WAVE);
-            if (lane >= d) incl += t;
+            const int u = __shfl_up(incl, d, WAVE);
+            if (lane >= d) incl += u;
         }
-        if (lane == WAVE - 1) wsum[wv] = incl;
+        if (lane == WAVE - 1) wsum[t][wv] = incl;
         __syncthreads();
-        int before = carry, tile = 0;
+        int ex = carry + incl - tsum, tile = 0;
         for (int w = 0; w < 1024 / WAVE; w++) {
-            const int ws = wsum[w];
-            before += (w < wv) ? ws : 0;
+            const int ws = wsum[t][w];
+            ex += (w < wv) ? ws : 0;
             tile += ws;
         }
-        int ex = before + incl - tsum;
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            if (k0 + q < m) {
-                out[k0 + q] = ex;
-                count[k0 + q] = 0;
-                count[m + k0 + q] = 0;
-            }
-            ex += v[q];
+        const int4 o = make_int4(ex, ex + v.x, ex + v.x + v.y, ex + v.x + v.y + v.z);
+        if (k0 + 3 < m) {
+            *(int4*)(out + k0) = o;
+        } else {
+            if (k0 < m) out[k0] = o.x;
+            if (k0 + 1 < m) out[k0 + 1] = o.y;
+            if (k0 + 2 < m) out[k0 + 2] = o.z;
         }
         carry += tile;
-        __syncthreads();
     }
     if (threadIdx.x == 0) out[m] = carry;
 }
@@ -136,7 +144,7 @@ k_scan_one(int m, int* __restrict__ count, int* __restrict__ out)
 constexpr int SCAN_PER_BLOCK = 1024;
 
 __global__ void __launch_bounds__(BLOCK)
-k_scan_local(int m, int* __restrict__ in, int* __restrict__ out, int* __restrict__ blocksum)
+k_scan_local(int m, const int* __restrict__ in, int* __restrict__ out, int* __restrict__ blocksum)
 {
     __shared__ int sh[BLOCK];
     int base = blockIdx.x * SCAN_PER_BLOCK + threadIdx.x * 4;
@@ -150,11 +158,7 @@ k_scan_local(int m, int* __restrict__ in, int* __restrict__ out, int* __restrict
     int excl = block_excl_scan(s, sh, &total);
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        if (base + q < m) {
-            out[base + q] = excl;
-            in[base + q] = 0;  // counts and scatter cursors start at zero next build
-            in[m + base + q] = 0;
-        }
+        if (base + q < m) out[base + q] = excl;
         excl += v[q];
     }
     if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
@@ -204,7 +208,7 @@ k_rank(int n, const int* __restrict__ perm_tmp, const int* __restrict__ bin_of,
        const int* __restrict__ bin_start, const double* __restrict__ pos,
        const int32_t* __restrict__ type_copy, const double4* __restrict__ shift,
        int* __restrict__ perm, double4* __restrict__ pos_s, double4* __restrict__ shift_s,
-       double4* __restrict__ ref_s, int nbins, int* __restrict__ slab)
+       double4* __restrict__ ref_s, int nbins, int* __restrict__ slab, int* __restrict__ count)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -214,6 +218,10 @@ k_rank(int n, const int* __restrict__ perm_tmp, const int* __restrict__ bin_of,
     int rank = 0;
     for (int q = s; q < e; q++) rank += (perm_tmp[q] < v) ? 1 : 0;
     const int o = s + rank;
+    // the bin's count and scatter cursor are spent: leave them at zero for
+    // the next build (every atom of the bin writes the same zeros)
+    count[b] = 0;
+    count[nbins + b] = 0;
     // XCD slabs of bins holding equal shares of the sorted atoms: slab x
     // starts at the bin of sorted atom floor(n x / 8)
 #pragma unroll
@@ -483,9 +491,9 @@ void launch_bin(int n, const double* pos, const int32_t* type, int n_elem,
                        type, n_elem, g, bin_of, shift, count, type_copy, status);
 }
 
-void launch_scan(int nbins, int* count, int* bin_start, int* tmp, hipStream_t s)
+void launch_scan(int nbins, const int* count, int* bin_start, int* tmp, hipStream_t s)
 {
-    if (nbins <= 65536) {
+    if (nbins <= SCAN_ONE_MAX) {
         hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, s, nbins, count, bin_start);
         return;
     }
@@ -508,12 +516,12 @@ void launch_scatter(int n, const int* bin_of, const int* bin_start, int* fill,
 void launch_rank(int n, const int* perm_tmp, const int* bin_of, const int* bin_start,
                  const double* pos, const int32_t* type_copy, const double4* shift,
                  int* perm, double4* pos_s, double4* shift_s, double4* ref_s, int nbins,
-                 int* slab, hipStream_t s)
+                 int* slab, int* count, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_rank, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s, n, perm_tmp,
                        bin_of, bin_start, pos, type_copy, shift, perm, pos_s, shift_s,
-                       ref_s, nbins, slab);
+                       ref_s, nbins, slab, count);
 }
 
 void launch_update(int n, const double* pos, const int* perm,

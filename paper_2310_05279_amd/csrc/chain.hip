@@ -132,19 +132,34 @@ k_final(int na, const double* __restrict__ part_a, int nb, const double* __restr
     __shared__ double fin[1024 / WAVE][8];
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     const int nmax = na > nb ? na : nb;
-    for (int b = threadIdx.x; b < nmax; b += 1024) {
-        const double4 z = make_double4(0.0, 0.0, 0.0, 0.0);
-        const double4* pa = (const double4*)(part_a + (size_t)b * 8);
-        const double4* pb = (const double4*)(part_b + (size_t)b * 8);
-        const double4 a0 = b < na ? pa[0] : z, a1 = b < na ? pa[1] : z;
-        const double4 c0 = b < nb ? pb[0] : z, c1 = b < nb ? pb[1] : z;
-        acc[0] += a0.x + c0.x;
-        acc[1] += a0.y + c0.y;
-        acc[2] += a0.z + c0.z;
-        acc[3] += a0.w + c0.w;
-        acc[4] += a1.x + c1.x;
-        acc[5] += a1.y + c1.y;
-        acc[6] += a1.z + c1.z;
+    // four rows of partials per thread and pass, loaded before any is used;
+    // rows past a pass's count load its last row and are weighted by zero
+    for (int b0 = threadIdx.x; b0 < nmax; b0 += 4 * 1024) {
+        double4 a0[4], a1[4], c0[4], c1[4];
+        double sa[4], sb[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int b = b0 + r * 1024;
+            const int ba = b < na ? b : na - 1, bb = b < nb ? b : nb - 1;
+            sa[r] = b < na ? 1.0 : 0.0;
+            sb[r] = b < nb ? 1.0 : 0.0;
+            const double4* pa = (const double4*)(part_a + (size_t)ba * 8);
+            const double4* pb = (const double4*)(part_b + (size_t)bb * 8);
+            a0[r] = pa[0];
+            a1[r] = pa[1];
+            c0[r] = pb[0];
+            c1[r] = pb[1];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            acc[0] += sa[r] * a0[r].x + sb[r] * c0[r].x;
+            acc[1] += sa[r] * a0[r].y + sb[r] * c0[r].y;
+            acc[2] += sa[r] * a0[r].z + sb[r] * c0[r].z;
+            acc[3] += sa[r] * a0[r].w + sb[r] * c0[r].w;
+            acc[4] += sa[r] * a1[r].x + sb[r] * c1[r].x;
+            acc[5] += sa[r] * a1[r].y + sb[r] * c1[r].y;
+            acc[6] += sa[r] * a1[r].z + sb[r] * c1[r].z;
+        }
     }
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     wave_sums(acc);

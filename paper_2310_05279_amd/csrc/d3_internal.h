@@ -51,13 +51,13 @@ struct PairScal {
 void launch_bin(int n, const double* pos, const int32_t* type, int n_elem,
                 const Geo& g, int* bin_of, double4* shift, int* count,
                 int32_t* type_copy, int* status, hipStream_t s);
-void launch_scan(int nbins, int* count, int* bin_start, int* tmp, hipStream_t s);
+void launch_scan(int nbins, const int* count, int* bin_start, int* tmp, hipStream_t s);
 void launch_scatter(int n, const int* bin_of, const int* bin_start, int* fill,
                     int* perm_tmp, hipStream_t s);
 void launch_rank(int n, const int* perm_tmp, const int* bin_of, const int* bin_start,
                  const double* pos, const int32_t* type_copy, const double4* shift,
                  int* perm, double4* pos_s, double4* shift_s, double4* ref_s, int nbins,
-                 int* slab, hipStream_t s);
+                 int* slab, int* count, hipStream_t s);
 void launch_list(int n, const double4* pos_s, const int* bin_start, const int* slab, const Geo& g,
                  const double4* img_tab, double rp2, double rc2, uint32_t* list_p,
                  int* cnt_p, int cap_p, uint32_t* list_c, int* cnt_c, int cap_c,
