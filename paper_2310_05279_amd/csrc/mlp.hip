@@ -123,6 +123,16 @@ __device__ void exact_c6(const ElemTab* tab, const double* __restrict__ c6ref, i
     out[2] = d2;
 }
 
+// exact_c6 behind a call, so that its registers do not count against the
+// surrogate dispersion pass, which needs it only for CNs outside the box
+__device__ __noinline__ double2 exact_c6_call(const ElemTab* tab, const double* __restrict__ c6ref,
+                                             int zi, int zj, double ni, double nj)
+{
+    double ex[3];
+    exact_c6(tab, c6ref, zi, zj, ni, nj, ex);
+    return make_double2(ex[0], ex[1]);
+}
+
 __global__ void __launch_bounds__(BLOCK)
 k_exact_eval(int m, const int32_t* __restrict__ ei, const int32_t* __restrict__ ej,
              const double* __restrict__ ni, const double* __restrict__ nj,
@@ -589,7 +599,7 @@ k_sur_eval(int m, const int32_t* __restrict__ ei, const int32_t* __restrict__ ej
 // list is first sorted by the neighbour's element in LDS, so every 64-entry
 // step uses a single network.
 template <bool IMG>
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
 k_pair_sur(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_tab,
            int n_img, int img_bits, const uint32_t* __restrict__ list_p,
            const int* __restrict__ cnt_p, int cap_p, const ElemTab* __restrict__ tab,
@@ -675,7 +685,6 @@ k_pair_sur(int n, const double4* __restrict__ pos_s, const double4* __restrict__
                 int p;
                 bool sw;
                 order_query(zi, f, ne, &p, &sw);
-                const float* sm = s_small + p * SMALL;
                 bf16x8 ah[2], al[2];
                 for (int blk = 0; blk < 2; blk++) {
                     ah[blk] = sv.a_hi[((size_t)p * 2 + blk) * WAVE + lane];
@@ -700,15 +709,20 @@ k_pair_sur(int n, const double4* __restrict__ pos_s, const double4* __restrict__
                     const float xa = (float)(2.0 * ni / cn_hi - 1.0);
                     const float xb = (float)(2.0 * nj / cn_hi - 1.0);
                     float y[3];
-                    mlp64(sw ? xb : xa, sw ? xa : xb, sm, ah, al, y);
+                    // the weights are re-read from LDS every step rather than held in
+                    // registers across the loop (an opaque offset keeps them from being
+                    // hoisted), which leaves room for three waves per SIMD
+                    int smo = p * SMALL;
+                    asm volatile("" : "+v"(smo));
+                    mlp64(sw ? xb : xa, sw ? xa : xb, s_small + smo, ah, al, y);
                     float c6 = y[0] * st3 + st0;
                     const float da = y[1] * st4 + st1, db = y[2] * st5 + st2;
                     float dc6 = sw ? db : da;
                     if (ni > (double)cn_hi || nj > (double)cn_hi) {
-                        double ex[3];  // exact Eq. 3 outside the trained box
-                        exact_c6(tab, c6ref, zi, f, ni, nj, ex);
-                        c6 = (float)ex[0];
-                        dc6 = (float)ex[1];
+                        // exact Eq. 3 outside the trained box (out of line: rare)
+                        const double2 ex = exact_c6_call(tab, c6ref, zi, f, ni, nj);
+                        c6 = (float)ex.x;
+                        dc6 = (float)ex.y;
                     }
                     c6 = in ? c6 : 0.0f;
                     dc6 = in ? dc6 : 0.0f;
