@@ -127,6 +127,32 @@ def test_single_reference_table():
     compare(gpu, ref, 800, label="k1")
 
 
+def test_twelve_element_table():
+    """A 12-element table, beyond the eight elements whose C6 table the
+    dispersion pass stages in LDS: parity on a random periodic cell."""
+    tab12 = synth.make_table(seed=77, n_elem=12)
+    m = synth.mof_like(900, seed=13)
+    types = np.random.default_rng(12).integers(0, 12, 900).astype(np.int32)
+    s = {"pos": m["pos"], "types": types, "cell": m["cell"], "pbc": m["pbc"]}
+    ref = R.d3(s["pos"], types, s["cell"], s["pbc"], tab12)
+    gpu = run_gpu(s, table=tab12)
+    compare(gpu, ref, 900, label="12 elements")
+
+
+def test_dense_cell_long_cutoffs():
+    """R_pot = 30 A and R_cn = 10 A on a dense 1 500-atom cell smaller than
+    the cutoff: the list build's bins then hold ~190 atoms (several groups
+    of 64 per wave), lists exceed 9 000 entries and images reach two cells
+    out."""
+    m = synth.mof_like(1500, density=0.08, seed=14)
+    prm = dict(r_pot=30.0, r_cn=10.0)
+    ref = R.d3(m["pos"], m["types"], m["cell"], m["pbc"], TAB, **prm)
+    gpu = run_gpu(m, prm=prm)
+    print("dense: list stats %s" % gpu["stats"], flush=True)
+    assert gpu["stats"]["max_pot"] > 8000
+    compare(gpu, ref, 1500, label="dense")
+
+
 def test_mof_24000_plain_config2():
     """The 24 000-atom MOF-like cell: full comparison with the C oracle."""
     m = synth.mof_like(24000)
@@ -136,12 +162,19 @@ def test_mof_24000_plain_config2():
     assert np.abs(gpu["cn"] - ref["cn"]).max() < 1e-12
 
 
-@pytest.mark.parametrize("case", ["graphene", "mof"])
+@pytest.mark.parametrize("case", ["graphene", "mof", "tiny"])
 def test_precision_form(case):
-    """FP32 pair arithmetic with FP64 cutoffs, weights and accumulation."""
+    """FP32 pair arithmetic with FP64 cutoffs, weights and accumulation
+    (the tiny triclinic cell takes the path with images outside LDS)."""
     if case == "graphene":
         s = synth.bilayer_graphene(12, 12, seed=3)
         ref = R.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB)
+    elif case == "tiny":
+        cell = np.array([[5.0, 0.0, 0.0], [2.0, 4.6, 0.0], [0.5, 0.7, 5.3]])
+        frac = np.random.default_rng(2).uniform(0, 1, (4, 3))
+        s = {"pos": frac @ cell, "types": np.array([0, 1, 2, 4], np.int32), "cell": cell,
+             "pbc": np.array([1, 1, 1], np.int32)}
+        ref = O.d3(s["pos"], s["types"], cell, s["pbc"], TAB)
     else:
         s = synth.mof_like(3000, seed=31)
         ref = R.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB)
