@@ -6,6 +6,8 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <mutex>
+#include <atomic>
 
 #include "d3_ctx.h"
 
@@ -152,6 +154,53 @@ int make_geo(const double* cell, const int32_t* pbc, double rlist, int64_t n,
     return D3_OK;
 }
 
+static int device_cus()
+{
+    static std::atomic<int> ncu{0};
+    int v = ncu.load();
+    if (v > 0) return v;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1)
+        v = 256;
+    ncu.store(v);
+    return v;
+}
+
+int max_pass_blocks()
+{
+    const int waves = MAX_WAVES_PER_SIMD * 4 * device_cus();
+    return ((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK + 7) / 8 * 8;
+}
+
+int pass_blocks(const void* kernel, int units, size_t dyn_lds)
+{
+    // resident workgroups per CU of each kernel, from the runtime's occupancy
+    static std::mutex mu;
+    static std::vector<std::pair<const void*, int>> cache;
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (const auto& kv : cache)
+            if (kv.first == kernel) per_cu = kv.second;
+        if (per_cu == 0) {
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, BLOCK, dyn_lds) !=
+                    hipSuccess || nb < 1)
+                nb = 1;
+            (void)hipGetLastError();
+            cache.emplace_back(kernel, nb);
+            per_cu = nb;
+        }
+    }
+    const long cus = device_cus();
+    const long resident = (long)per_cu * WAVES_PER_BLOCK * cus;
+    long waves = units < 1 ? 1 : units;
+    if (waves <= 8 * resident) waves = waves < resident ? waves : resident;
+    else waves = std::min(waves, (long)MAX_WAVES_PER_SIMD * 4 * cus);
+    return (int)(((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK + 7) / 8 * 8);
+}
+
 void phase_mark(d3_ctx* c, int phase, hipStream_t s)
 {
     if (!c->timing) return;
@@ -221,9 +270,9 @@ int alloc_atoms(d3_ctx* c, int64_t n)
     D3CHK(ensure(c->U, N * sizeof(double)));
     D3CHK(ensure(c->cnt_p, N * sizeof(int)));
     D3CHK(ensure(c->cnt_c, N * sizeof(int)));
-    const size_t nw = (size_t)pass_waves((int)n);
-    D3CHK(ensure(c->vpart, (nw / WAVES_PER_BLOCK) * 8 * sizeof(double)));
-    D3CHK(ensure(c->vpart2, (nw / WAVES_PER_BLOCK) * 8 * sizeof(double)));
+    const size_t nb = (size_t)max_pass_blocks();
+    D3CHK(ensure(c->vpart, nb * 8 * sizeof(double)));
+    D3CHK(ensure(c->vpart2, nb * 8 * sizeof(double)));
     return D3_OK;
 }
 
@@ -672,10 +721,11 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
     sc.rp2 = c->prm.r_pot * c->prm.r_pot;
     sc.rc2 = c->prm.r_cn * c->prm.r_cn;
     phase_mark(c, PH_PAIR, s);
+    int na = 0;
     if (mode == D3_MODE_SURROGATE) {
-        D3CHK(surrogate_pair(c, sc, s));
+        D3CHK(surrogate_pair(c, sc, s, &na));
     } else {
-        launch_pair(mode, n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img,
+        na = launch_pair(mode, n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img,
                     g.img_bits, c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p,
                     c->d_tab.as<ElemTab>(), c->d_c6.as<double>(), c->d_pc.as<double4>(), sc,
                     c->w.as<double>(), c->wd.as<double>(), c->P.as<double>(), c->Pf.as<float>(),
@@ -685,13 +735,13 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
     }
     phase_mark(c, PH_PAIR, s);
     phase_mark(c, PH_CHAIN, s);
-    launch_chain(mode == D3_MODE_PLAIN_F64 ? D3_MODE_PLAIN_F64 : D3_MODE_PREC_F32, n,
+    const int nb = launch_chain(mode == D3_MODE_PLAIN_F64 ? D3_MODE_PLAIN_F64 : D3_MODE_PREC_F32, n,
                  c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img, g.img_bits,
                  c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, c->d_tab.as<ElemTab>(),
                  sc.rc2, c->G.as<double>(), c->Fp.as<double>(), c->U.as<double>(),
                  c->perm.as<int>(), forces, atom_energy, acc, c->vpart2.as<double>(), s);
     HIPCHK(hipGetLastError());
-    launch_final(n, c->vpart.as<double>(), c->vpart2.as<double>(), energy, virial, acc, s);
+    launch_final(na, c->vpart.as<double>(), nb, c->vpart2.as<double>(), energy, virial, acc, s);
     phase_mark(c, PH_CHAIN, s);
     HIPCHK(hipGetLastError());
     return D3_OK;

@@ -540,10 +540,10 @@ void launch_list(int n, const double4* pos_s, const int* bin_start, const int* s
                  int count_only, int* status, hipStream_t s)
 {
     if (n <= 0) return;
-    const dim3 grid(split_blocks(g.nbins)), block(BLOCK);
 #define D3_LIST(I, C)                                                                          \
-    hipLaunchKernelGGL((k_list<I, C>), grid, block, 0, s, pos_s, bin_start, slab, g, img_tab, rp2, \
-                       rc2, list_p, cnt_p, cap_p, list_c, cnt_c, cap_c, status)
+    hipLaunchKernelGGL((k_list<I, C>), dim3(pass_blocks((const void*)&k_list<I, C>, g.nbins)), \
+                       dim3(BLOCK), 0, s, pos_s, bin_start, slab, g, img_tab, rp2, rc2, list_p,  \
+                       cnt_p, cap_p, list_c, cnt_c, cap_c, status)
     const bool lds = g.n_img <= IMG_LDS;
     if (count_only) {
         if (lds) D3_LIST(true, true);

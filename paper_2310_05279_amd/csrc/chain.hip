@@ -11,8 +11,6 @@ namespace d3 {
 
 constexpr int ROW = 16;  // lanes per atom: four atoms per wave, one per DPP row
 
-static int chain_blocks(int n) { return split_blocks((n + WAVE / ROW - 1) / (WAVE / ROW)); }
-
 template <bool F32, bool IMG>
 __global__ void __launch_bounds__(BLOCK)
 k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_tab, int n_img,
@@ -197,34 +195,39 @@ k_scatter_out(int n, const double* __restrict__ src, const int* __restrict__ per
     if (k < n) dst[perm[k]] = src[k];
 }
 
-void launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
-                  int img_bits, const uint32_t* list_c, const int* cnt_c, int cap_c,
-                  const ElemTab* tab, double rc2, const double* G, const double* Fp,
-                  const double* U, const int* perm, double* forces, double* atom_energy,
-                  int accumulate, double* part, hipStream_t s)
+int launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
+                 int img_bits, const uint32_t* list_c, const int* cnt_c, int cap_c,
+                 const ElemTab* tab, double rc2, const double* G, const double* Fp,
+                 const double* U, const int* perm, double* forces, double* atom_energy,
+                 int accumulate, double* part, hipStream_t s)
 {
-    if (n <= 0) return;
-    const dim3 grid(chain_blocks(n)), block(BLOCK);
+    if (n <= 0) return 0;
+    const int groups = (n + WAVE / ROW - 1) / (WAVE / ROW);
     const bool lds = n_img <= IMG_LDS;
+    int nblk = 0;
 #define D3_CHAIN(F, I)                                                                          \
-    hipLaunchKernelGGL((k_chain<F, I>), grid, block, 0, s, n, pos_s, img_tab, n_img, img_bits,  \
-                       list_c, cnt_c, cap_c, tab, rc2, G, Fp, U, perm, forces, atom_energy,     \
-                       accumulate, part)
+    {                                                                                           \
+        nblk = pass_blocks((const void*)&k_chain<F, I>, groups);                                \
+        hipLaunchKernelGGL((k_chain<F, I>), dim3(nblk), dim3(BLOCK), 0, s, n, pos_s, img_tab,   \
+                           n_img, img_bits, list_c, cnt_c, cap_c, tab, rc2, G, Fp, U, perm,     \
+                           forces, atom_energy, accumulate, part);                              \
+    }
     if (mode == D3_MODE_PREC_F32) {
-        if (lds) D3_CHAIN(true, true);
-        else D3_CHAIN(true, false);
+        if (lds) D3_CHAIN(true, true)
+        else D3_CHAIN(true, false)
     } else {
-        if (lds) D3_CHAIN(false, true);
-        else D3_CHAIN(false, false);
+        if (lds) D3_CHAIN(false, true)
+        else D3_CHAIN(false, false)
     }
 #undef D3_CHAIN
+    return nblk;
 }
 
-void launch_final(int n, const double* part_a, const double* part_b, double* energy,
+void launch_final(int na, const double* part_a, int nb, const double* part_b, double* energy,
                   double* virial, int accumulate, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, s, split_blocks(n), part_a, chain_blocks(n), part_b,
-                       energy, virial, accumulate);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, s, na, part_a, nb, part_b, energy, virial,
+                       accumulate);
 }
 
 void launch_scatter_out(int n, const double* src, const int* perm, double* dst, hipStream_t s)

@@ -104,11 +104,12 @@ void launch_cn(int mode, int n, const double4* pos_s, const double4* img_tab, in
                float* Wf, hipStream_t s)
 {
     if (n <= 0) return;
-    const dim3 grid(split_blocks((n + WAVE / ROW - 1) / (WAVE / ROW))), block(BLOCK);
+    const int groups = (n + WAVE / ROW - 1) / (WAVE / ROW);
     const bool lds = n_img <= IMG_LDS;
-#define D3_CN(F, I)                                                                          \
-    hipLaunchKernelGGL((k_cn<F, I>), grid, block, 0, s, n, pos_s, img_tab, n_img, img_bits,  \
-                       list_c, cnt_c, cap_c, tab, rc2, cn, w, wd, W, Wf)
+#define D3_CN(F, I)                                                                             \
+    hipLaunchKernelGGL((k_cn<F, I>), dim3(pass_blocks((const void*)&k_cn<F, I>, groups)),       \
+                       dim3(BLOCK), 0, s, n, pos_s, img_tab, n_img, img_bits, list_c, cnt_c,    \
+                       cap_c, tab, rc2, cn, w, wd, W, Wf)
     if (mode == D3_MODE_PREC_F32) {
         if (lds) D3_CN(true, true);
         else D3_CN(true, false);

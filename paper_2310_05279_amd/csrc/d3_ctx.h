@@ -110,6 +110,6 @@ int timing_flush(d3_ctx* c);
 
 // surrogate (mlp.hip)
 void surrogate_free(d3_ctx* c);
-int surrogate_pair(d3_ctx* c, const PairScal& sc, hipStream_t s);
+int surrogate_pair(d3_ctx* c, const PairScal& sc, hipStream_t s, int* nblk);
 
 }  // namespace d3

@@ -69,31 +69,32 @@ void launch_update(int n, const double* pos, const int* perm,
                    hipStream_t s);
 
 // ---- launchers (cn.hip, disp.hip, chain.hip) --------------------------
-// workgroups of the per-atom passes: up to 12 waves per SIMD, a whole
-// number of 8-workgroup groups (one group per XCD round)
-inline int split_blocks(int n)
-{
-    const int max_waves = 256 * 4 * 12;
-    if (n < 1) n = 1;
-    const int waves = n < max_waves ? n : max_waves;
-    return ((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK + 7) / 8 * 8;
-}
-inline int pass_waves(int n) { return split_blocks(n) * WAVES_PER_BLOCK; }
+// Workgroups of BLOCK threads for a pass whose waves take `units` work
+// items one at a time (atoms, groups of atoms, bins), a whole number of
+// 8-workgroup groups (one per XCD in turn).  When the resident waves of the
+// kernel (from its occupancy) would get at most 8 units each, the grid is
+// exactly the resident waves, so no tail round follows; otherwise it holds
+// up to MAX_WAVES_PER_SIMD waves per SIMD, so that waves finishing early
+// are replaced and the XCDs end together.
+constexpr int MAX_WAVES_PER_SIMD = 24;
+int pass_blocks(const void* kernel, int units, size_t dyn_lds = 0);
+// upper bound of pass_blocks on this device (sizing of per-block partials)
+int max_pass_blocks();
 void launch_cn(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
                int img_bits, const uint32_t* list_c, const int* cnt_c, int cap_c,
                const ElemTab* tab, double rc2, double* cn, double* w, double* wd, double* W,
                float* Wf, hipStream_t s);
-void launch_pair(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
+int launch_pair(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
                  int img_bits, const uint32_t* list_p, const int* cnt_p, int cap_p,
                  const ElemTab* tab, const double* c6ref, const double4* pc, PairScal sc,
                  const double* w, const double* wd, const double* W, const float* Wf, double* Fp,
                  double* U, double* G, double* part, hipStream_t s);
-void launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
+int launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
                   int img_bits, const uint32_t* list_c, const int* cnt_c, int cap_c,
                   const ElemTab* tab, double rc2, const double* G, const double* Fp,
                   const double* U, const int* perm, double* forces, double* atom_energy,
                   int accumulate, double* part, hipStream_t s);
-void launch_final(int n, const double* part_a, const double* part_b, double* energy,
+void launch_final(int na, const double* part_a, int nb, const double* part_b, double* energy,
                   double* virial, int accumulate, hipStream_t s);
 void launch_scatter_out(int n, const double* src, const int* perm, double* dst, hipStream_t s);
 

@@ -241,26 +241,31 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
     block_partials(vals, part);
 }
 
-void launch_pair(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
-                 int img_bits, const uint32_t* list_p, const int* cnt_p, int cap_p,
-                 const ElemTab* tab, const double* c6ref, const double4* pc, PairScal sc,
-                 const double* w, const double* wd, const double* W, const float* Wf, double* Fp,
-                 double* U, double* G, double* part, hipStream_t s)
+int launch_pair(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
+                int img_bits, const uint32_t* list_p, const int* cnt_p, int cap_p,
+                const ElemTab* tab, const double* c6ref, const double4* pc, PairScal sc,
+                const double* w, const double* wd, const double* W, const float* Wf, double* Fp,
+                double* U, double* G, double* part, hipStream_t s)
 {
-    if (n <= 0) return;
-    const dim3 grid(split_blocks(n)), block(BLOCK);
+    if (n <= 0) return 0;
     const bool lds = n_img <= IMG_LDS;
-#define D3_PAIR(F, I)                                                                          \
-    hipLaunchKernelGGL((k_pair<F, I>), grid, block, 0, s, n, pos_s, img_tab, n_img, img_bits,  \
-                       list_p, cnt_p, cap_p, tab, c6ref, pc, sc, w, wd, W, Wf, Fp, U, G, part)
+    int nblk = 0;
+#define D3_PAIR(F, I)                                                                           \
+    {                                                                                           \
+        nblk = pass_blocks((const void*)&k_pair<F, I>, n);                                      \
+        hipLaunchKernelGGL((k_pair<F, I>), dim3(nblk), dim3(BLOCK), 0, s, n, pos_s, img_tab,    \
+                           n_img, img_bits, list_p, cnt_p, cap_p, tab, c6ref, pc, sc, w, wd, W, \
+                           Wf, Fp, U, G, part);                                                 \
+    }
     if (mode == D3_MODE_PREC_F32) {
-        if (lds) D3_PAIR(true, true);
-        else D3_PAIR(true, false);
+        if (lds) D3_PAIR(true, true)
+        else D3_PAIR(true, false)
     } else {
-        if (lds) D3_PAIR(false, true);
-        else D3_PAIR(false, false);
+        if (lds) D3_PAIR(false, true)
+        else D3_PAIR(false, false)
     }
 #undef D3_PAIR
+    return nblk;
 }
 
 }  // namespace d3

@@ -872,8 +872,9 @@ static SurView view(const d3_ctx* c)
     return v;
 }
 
-int surrogate_pair(d3_ctx* c, const PairScal& sc, hipStream_t st)
+int surrogate_pair(d3_ctx* c, const PairScal& sc, hipStream_t st, int* nblk)
 {
+    *nblk = 0;
     if (!c->sur || !c->sur->trained)
         return fail(D3_ERR_NOT_TRAINED, "surrogate mode before training or loading weights");
     if (c->n_elem > SUR_ELEM)
@@ -881,16 +882,18 @@ int surrogate_pair(d3_ctx* c, const PairScal& sc, hipStream_t st)
     const int n = (int)c->n;
     if (n <= 0) return D3_OK;
     const Geo& g = c->geo;
-    const dim3 grid(split_blocks(n)), block(BLOCK);
+    const dim3 block(BLOCK);
     if (g.n_img <= IMG_LDS)
-        hipLaunchKernelGGL((k_pair_sur<true>), grid, block, 0, st, n, c->pos_s.as<double4>(),
+        hipLaunchKernelGGL((k_pair_sur<true>),
+                           dim3(*nblk = pass_blocks((const void*)&k_pair_sur<true>, n)), block, 0, st, n, c->pos_s.as<double4>(),
                            c->img_tab.as<double4>(), g.n_img, g.img_bits, c->list_p.as<uint32_t>(),
                            c->cnt_p.as<int>(), c->cap_p, c->d_tab.as<ElemTab>(),
                            c->d_c6.as<double>(), c->d_pc.as<double4>(), sc, c->cn.as<double>(),
                            view(c), c->Fp.as<double>(), c->U.as<double>(), c->G.as<double>(),
                            c->vpart.as<double>());
     else
-        hipLaunchKernelGGL((k_pair_sur<false>), grid, block, 0, st, n, c->pos_s.as<double4>(),
+        hipLaunchKernelGGL((k_pair_sur<false>),
+                           dim3(*nblk = pass_blocks((const void*)&k_pair_sur<false>, n)), block, 0, st, n, c->pos_s.as<double4>(),
                            c->img_tab.as<double4>(), g.n_img, g.img_bits, c->list_p.as<uint32_t>(),
                            c->cnt_p.as<int>(), c->cap_p, c->d_tab.as<ElemTab>(),
                            c->d_c6.as<double>(), c->d_pc.as<double4>(), sc, c->cn.as<double>(),
