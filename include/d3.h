@@ -36,6 +36,15 @@
  *    d3_last_error() then holds a message (per calling thread).
  *  - One context may be used by one host thread at a time.  Calls on one
  *    context must be ordered (same stream, or synchronised by the caller).
+ *  - Stream capture (HIP graphs): once a build of the same (n, cell, pbc)
+ *    and the same call in the same mode have completed on the context
+ *    (so that every buffer exists), d3_build_neighbors,
+ *    d3_coordination and d3_energy_forces_virial (n > 0, flags without
+ *    D3_AUTO_REBUILD, timing off) enqueue kernels only: no allocation,
+ *    memset, copy or synchronisation, so they may be captured and the
+ *    graph replayed on new positions written into the same buffers.
+ *    d3_status, d3_list_stats, the first build of a geometry and
+ *    D3_AUTO_REBUILD synchronise and must stay outside a capture.
  */
 #ifndef D3_MI355X_H
 #define D3_MI355X_H
@@ -241,7 +250,8 @@ int d3_c6_surrogate_set_weights(d3_ctx *ctx, const float *host_buf,
                                 int64_t bytes);
 
 /* One training step on explicit samples (tests: gradient check against
- * the CPU reference).  x: device float[m*2] (cn_i, cn_j), y: device
+ * the CPU reference).  x: device float[m*2], the network inputs (cn_i,
+ * cn_j) already mapped to [-1, 1] by x = 2 cn / cn_hi - 1; y: device
  * float[m*3] standardised targets, pair: device int32[m]; grads: device
  * float[pairs*1251] receives the mean-squared-error gradient; loss: device
  * float[1].  No weight update. */
