@@ -31,6 +31,15 @@ potential", Sec. II A):
   part through dE/dn_k.
 * virial, Eq. 7 summed over atoms: W = -dE/d(strain), which for a finite
   cluster equals sum_i r_i (x) F_i (eV).
+* per-atom virial, Eq. 7: W_i = sum over the entries (i, j, T) of i of the
+  entry's term of W, -1/2 [phi'(r) 1(r < R_pot) + (G_i + G_j) f'(r)
+  1(r < R_cn)] r (x) r / r.  Each unordered pair's term is split half and
+  half between its two atoms, so sum_i W_i = W exactly.  For the direct
+  part this is Eq. 7 as printed (r_ij (x) dU_j/dr_ji at fixed C6); the
+  paper's formula assumes U_j depends on its own neighbour vectors only,
+  which D3's coordination numbers break, and the chain part is given the
+  same half-and-half split.
+* per-atom heat current, Eq. 8: J_i = W_i v_i.
 
 Units: Angstrom and eV.  The table arrives in Hartree*bohr^6 (C6) and bohr
 (r2r4) and is converted here with CODATA 2018 constants.
@@ -234,8 +243,21 @@ def _evaluate(n, types, tab, prm, i, j, d, cn=None):
     for k in range(3):
         forces[:, k] += np.bincount(ic, weights=coef * dc[:, k], minlength=n)
     vir += -0.5 * np.einsum("e,ea,eb->ab", coef, dc, dc)
+    # Eq. 7 per atom: every entry's term goes to the atom that owns it
+    atom_vir = np.zeros((n, 3, 3))
+    for a in range(3):
+        for b in range(3):
+            atom_vir[:, a, b] = -0.5 * (
+                np.bincount(ip, weights=dphi_r * dp[:, a] * dp[:, b], minlength=n) +
+                np.bincount(ic, weights=coef * dc[:, a] * dc[:, b], minlength=n))
     return {"energy": float(atom_e.sum()), "forces": forces, "virial": vir,
-            "atom_energy": atom_e, "cn": cn, "dedn": dedn}
+            "atom_energy": atom_e, "atom_virial": atom_vir, "cn": cn, "dedn": dedn}
+
+
+def heat_current(atom_virial, vel):
+    """Eq. 8: J_i = W_i v_i for per-atom virials (N,3,3) and velocities
+    (N,3)."""
+    return np.einsum("iab,ib->ia", np.asarray(atom_virial), np.asarray(vel, dtype=np.float64))
 
 
 def energy_only(pos, types, cell, pbc, table, prm=None):
@@ -256,8 +278,9 @@ def energy_only(pos, types, cell, pbc, table, prm=None):
 
 
 def sampled(pos, types, cell, pbc, table, idx, prm=None):
-    """Forces, site energies, coordination numbers and dE/dn of the atoms
-    ``idx`` of a large cell, each computed from its own neighbourhood.
+    """Forces, site energies, per-atom virials, coordination numbers and
+    dE/dn of the atoms ``idx`` of a large cell, each computed from its own
+    neighbourhood.
 
     The force on k depends on n_j for j within R_pot of k and on dE/dn_j for
     j within R_cn of k; dE/dn_j depends on n_l for l within R_pot of j, and
@@ -270,7 +293,7 @@ def sampled(pos, types, cell, pbc, table, idx, prm=None):
     types = np.asarray(types, dtype=np.int64)
     rbig = prm.r_pot + 2.0 * prm.r_cn + 1e-6
     nvec, tvec = translations(cell, pbc, rbig, pos)
-    res = {"forces": [], "atom_energy": [], "cn": [], "dedn": []}
+    res = {"forces": [], "atom_energy": [], "atom_virial": [], "cn": [], "dedn": []}
     for k in np.asarray(idx):
         loc_pos, loc_atom = [], []
         for T in tvec:
@@ -317,12 +340,16 @@ def sampled(pos, types, cell, pbc, table, idx, prm=None):
         c6, _, _ = c6_eq3(zi, lt[m], np.full(zi.size, cn[me]), cn[m], tab)
         phi, dphi_r, _ = pair_terms(rr[m], zi, lt[m], c6, tab, prm)
         f = (dphi_r[:, None] * dd[m]).sum(0)
+        w = -0.5 * np.einsum("e,ea,eb->ab", dphi_r, dd[m], dd[m])
         mc = rr < prm.r_cn * prm.r_cn
         mc[me] = False
         rc = np.sqrt(rr[mc])
         _, df = counting(rc, tab["rcov"][lt[me]] + tab["rcov"][lt[mc]])
-        f += (((g[me] + g[mc]) * df / rc)[:, None] * dd[mc]).sum(0)
+        coef = (g[me] + g[mc]) * df / rc
+        f += (coef[:, None] * dd[mc]).sum(0)
+        w += -0.5 * np.einsum("e,ea,eb->ab", coef, dd[mc], dd[mc])
         res["forces"].append(f)
+        res["atom_virial"].append(w)
         res["atom_energy"].append(0.5 * phi.sum())
         res["cn"].append(cn[me])
         res["dedn"].append(g[me])

@@ -15,7 +15,9 @@
  *   U_i, E    Eqs. 2 and 1 with C8 = C6 R0^2, R0^2 = 3 r2r4_i r2r4_j;
  *   F_i       exact -dE/dr_i: a direct term at fixed C6 plus the chain term
  *             through dE/dn (C6 depends on the coordination numbers);
- *   W         -dE/d(strain) = Eq. 7 summed over atoms.
+ *   W         -dE/d(strain) = Eq. 7 summed over atoms;
+ *   W_i       Eq. 7 per atom: the terms of W from the entries of atom i
+ *             (each pair's term split half and half between its atoms).
  * Per-atom partial virials are summed in atom order at the end, so the
  * result does not depend on the thread count.
  */
@@ -149,7 +151,7 @@ int d3ref_threads(void)
  * Full evaluation.  Table arrays: n_ref[ne], cn_ref[ne][5],
  * c6_au[ne][ne][5][5] (Hartree bohr^6), rcov[ne] (A), r2r4[ne] (bohr).
  * Outputs (any may be NULL except energy): forces[n][3], virial[9],
- * atom_energy[n], cn[n], dedn[n].  Returns the number of entries within
+ * atom_energy[n], cn[n], dedn[n], atom_virial[n][9].  Returns the number of entries within
  * R_pot (>= 0) or -1 on allocation failure.
  */
 long d3ref_evaluate(int n, const double *pos, const int *types,
@@ -159,7 +161,8 @@ long d3ref_evaluate(int n, const double *pos, const int *types,
                     const double *r2r4, double s6, double a1, double s8,
                     double a2, double r_pot, double r_cn, int n_threads,
                     double *energy, double *forces, double *virial,
-                    double *atom_energy, double *cn_out, double *dedn_out)
+                    double *atom_energy, double *cn_out, double *dedn_out,
+                    double *atom_virial)
 {
     double idcell[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
     int nopbc[3] = {0, 0, 0};
@@ -294,6 +297,14 @@ long d3ref_evaluate(int n, const double *pos, const int *types,
     if (atom_energy) memcpy(atom_energy, ue, sizeof(double) * n);
     if (cn_out) memcpy(cn_out, cn, sizeof(double) * n);
     if (dedn_out) memcpy(dedn_out, g, sizeof(double) * n);
+    if (atom_virial)
+        for (int i = 0; i < n; i++) {
+            const double *w = wv + 6 * (size_t)i;
+            double *o = atom_virial + 9 * (size_t)i;
+            o[0] = w[0]; o[1] = w[1]; o[2] = w[2];
+            o[3] = w[1]; o[4] = w[3]; o[5] = w[4];
+            o[6] = w[2]; o[7] = w[4]; o[8] = w[5];
+        }
     for (int i = 0; i < n; i++) { free(L[i].j); free(L[i].d); }
     free(L); free(cn); free(g); free(ue); free(fo); free(wv);
     free(c6); free(r0sq); free(tv);

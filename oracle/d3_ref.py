@@ -37,7 +37,7 @@ def _load():
         lib.d3ref_evaluate.restype = ctypes.c_long
         lib.d3ref_evaluate.argtypes = [I, P, P, P, P, I, P, P, P, P, P,
                                        D, D, D, D, D, D, I,
-                                       P, P, P, P, P, P]
+                                       P, P, P, P, P, P, P]
         lib.d3ref_threads.restype = I
         _lib = lib
     return _lib
@@ -73,12 +73,14 @@ def d3(pos, types, cell, pbc, table, s6=1.0, a1=0.4289, s8=0.7875, a2=4.4407,
     ae = np.zeros(n)
     cn = np.zeros(n)
     g = np.zeros(n)
+    av = np.zeros((n, 3, 3))
     total = lib.d3ref_evaluate(
         n, _ptr(pos), _ptr(types), _ptr(cellp), _ptr(pbcp), ne, _ptr(n_ref),
         _ptr(cn_ref), _ptr(c6), _ptr(rcov), _ptr(r2r4), s6, a1, s8, a2,
         r_pot, r_cn, int(n_threads), _ptr(energy), _ptr(forces),
-        _ptr(virial), _ptr(ae), _ptr(cn), _ptr(g))
+        _ptr(virial), _ptr(ae), _ptr(cn), _ptr(g), _ptr(av))
     if total < 0:
         raise MemoryError("d3ref_evaluate failed")
     return {"energy": float(energy[0]), "forces": forces, "virial": virial,
-            "atom_energy": ae, "cn": cn, "dedn": g, "n_entries": int(total)}
+            "atom_energy": ae, "atom_virial": av, "cn": cn, "dedn": g,
+            "n_entries": int(total)}

@@ -359,6 +359,115 @@ def test_virial_equals_r_cross_f_for_cluster():
                                           abs=1e-13)
 
 
+# ----------------------------------------- Eqs. 7-8 per atom -------------
+
+def _site_energies(pos, types, tab, prm):
+    return O.d3(pos, types, None, (0, 0, 0), tab, prm)["atom_energy"]
+
+
+def test_atom_virial_is_eq7_by_finite_differences():
+    """Eq. 7 as printed, W_i = sum_j r_ij (x) dU_j/dr_ji, with dU_j/dr_ji
+    taken by central differences of the site energy U_j (Eq. 2) while atom
+    i alone moves.  With one reference point per element C6 does not
+    depend on the coordination numbers, so U_j depends on r_i only through
+    r_ji and the formula is exact (catches a transposed product, a missing
+    half or a sign)."""
+    tab = _table(force_k=1)
+    c = synth.cluster(8, 3.5, seed=21)
+    prm = O.Params(r_pot=12.0, r_cn=9.0)
+    pos, types = c["pos"], c["types"]
+    res = O.d3(pos, types, None, (0, 0, 0), tab, prm)
+    n, h = pos.shape[0], 1e-5
+    dU = np.zeros((n, n, 3))  # dU[j, i, :] = dU_j / dr_i
+    for i in range(n):
+        for k in range(3):
+            p = pos.copy()
+            p[i, k] += h
+            up = _site_energies(p, types, tab, prm)
+            p[i, k] -= 2 * h
+            um = _site_energies(p, types, tab, prm)
+            dU[:, i, k] = (up - um) / (2 * h)
+    scale = np.abs(res["atom_virial"]).max()
+    for i in range(n):
+        w = np.zeros((3, 3))
+        for j in range(n):
+            if j != i:
+                w += np.outer(pos[j] - pos[i], dU[j, i])
+        assert np.abs(w - res["atom_virial"][i]).max() < 1e-7 * scale
+
+
+def test_heat_current_is_eq8_by_directional_differences():
+    """Eq. 8, J_i = W_i . v_i: for the same single-reference cluster,
+    J_i = sum_j r_ij (dU_j/dr_ji . v_i), the derivative of U_j along v_i
+    taken by central differences (catches W^T v in place of W v for a
+    non-symmetric tensor and a wrong velocity index)."""
+    tab = _table(force_k=1)
+    c = synth.cluster(7, 3.5, seed=22)
+    prm = O.Params(r_pot=12.0, r_cn=9.0)
+    pos, types = c["pos"], c["types"]
+    vel = np.random.default_rng(4).normal(size=pos.shape)
+    res = O.d3(pos, types, None, (0, 0, 0), tab, prm)
+    J = O.heat_current(res["atom_virial"], vel)
+    h = 1e-5
+    for i in range(pos.shape[0]):
+        p = pos.copy()
+        p[i] += h * vel[i]
+        up = _site_energies(p, types, tab, prm)
+        p[i] -= 2 * h * vel[i]
+        um = _site_energies(p, types, tab, prm)
+        du = (up - um) / (2 * h)
+        ji = sum((pos[j] - pos[i]) * du[j] for j in range(pos.shape[0]) if j != i)
+        assert np.abs(ji - J[i]).max() < 1e-7 * np.abs(J).max()
+
+
+def test_atom_virials_sum_to_strain_derivative():
+    """With coordination-dependent C6 (several reference points) the
+    per-atom virials of a periodic triclinic cell sum to -dE/d(strain),
+    taken by central differences of E under homogeneous strain, and each is
+    a symmetric tensor."""
+    tab = _table()
+    rng = np.random.default_rng(18)
+    cell = np.array([[7.6, 0.0, 0.0], [1.2, 7.0, 0.0], [-0.6, 0.9, 8.1]])
+    prm = O.Params(r_pot=8.0, r_cn=4.0)
+    for _ in range(200):
+        pos = rng.uniform(0, 1, (11, 3)) @ cell
+        ii, jj, d = O.entries(pos, cell, (1, 1, 1), 1.2)
+        if len(ii) == 0 and _min_gap_to_cutoffs(pos, cell, (1, 1, 1), prm) > 2e-3:
+            break
+    types = rng.integers(0, 5, 11).astype(np.int32)
+    res = O.d3(pos, types, cell, (1, 1, 1), tab, prm)
+    av = res["atom_virial"]
+    scale = np.abs(av).max()
+    assert np.abs(av - av.transpose(0, 2, 1)).max() < 1e-14 * scale
+    tot = av.sum(0)
+    h = 1e-6
+    for a in range(3):
+        for b in range(3):
+            e = np.zeros((3, 3))
+            e[a, b] = h
+            p1, c1 = _strained(pos, cell, e)
+            p2, c2 = _strained(pos, cell, -e)
+            ep = O.energy_only(p1, types, c1, (1, 1, 1), tab, prm)
+            em = O.energy_only(p2, types, c2, (1, 1, 1), tab, prm)
+            assert -(ep - em) / (2 * h) == pytest.approx(tot[a, b], abs=1e-7 * np.abs(tot).max())
+
+
+def test_atom_virial_splits_each_pair_evenly():
+    """A heteronuclear dimer inside R_cn, with CN-dependent C6: G_1 != G_2,
+    yet both atoms carry the same virial, half of the total (the chain term
+    (G_1 + G_2) f'(r) is shared evenly, not given to one atom)."""
+    tab = _table(force_k=(3, 4, 2, 5, 3))
+    pos, types = _dimer(1, 4, 2.3)
+    res = O.d3(pos, types, None, (0, 0, 0), tab, O.Params())
+    assert abs(res["dedn"][0] - res["dedn"][1]) > 1e-6 * np.abs(res["dedn"]).max()
+    av = res["atom_virial"]
+    assert np.abs(av[0] - av[1]).max() < 1e-14 * np.abs(av).max()
+    assert np.abs(av[0] + av[1] - res["virial"]).max() < 1e-14 * np.abs(av).max()
+    # the virial of a dimer is the outer product of the bond with the force
+    w = np.outer(pos[1] - pos[0], res["forces"][1])
+    assert np.abs(av.sum(0) - w).max() < 1e-13 * np.abs(w).max()
+
+
 # ------------------------------------------------------ invariances -------
 
 def test_invariances_translation_rotation_permutation():
@@ -462,7 +571,7 @@ def test_c_oracle_matches_numpy_oracle():
         a = O.d3(c["pos"], c["types"], c["cell"], c["pbc"], tab)
         b = R.d3(c["pos"], c["types"], c["cell"], c["pbc"], tab)
         assert b["energy"] == pytest.approx(a["energy"], rel=1e-12)
-        for k in ("forces", "virial", "atom_energy", "cn", "dedn"):
+        for k in ("forces", "virial", "atom_energy", "atom_virial", "cn", "dedn"):
             sc = max(np.abs(a[k]).max(), 1e-30)
             # dE/dn sums terms of both signs: looser relative bound
             tol = 1e-10 if k == "dedn" else 1e-12
@@ -482,6 +591,8 @@ def test_sampled_mode_matches_full():
     assert s["atom_energy"] == pytest.approx(full["atom_energy"][idx], rel=1e-11)
     assert s["cn"] == pytest.approx(full["cn"][idx], rel=1e-12)
     assert s["dedn"] == pytest.approx(full["dedn"][idx], rel=1e-10, abs=1e-14)
+    sw = np.abs(full["atom_virial"]).max()
+    assert np.abs(s["atom_virial"] - full["atom_virial"][idx]).max() < 1e-11 * sw
 
 
 # ------------------------------------------------- surrogate network ------
