@@ -39,10 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # dispatch), each scaled by what the same counter read for a 512 MiB device
 # copy (FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  The figure belongs to the
 # kernel sources it was taken with: when their hash differs it is not used.
-PAIR_TRAFFIC = {"fetch_kib": 24111.426, "write_kib": 1019.628,
+PAIR_TRAFFIC = {"fetch_kib": 24108.014, "write_kib": 1019.526,
                 "fetch_scale": 1.9999, "write_scale": 1.0,
                 "sources": ("disp.hip", "d3_device.h", "d3_internal.h"),
-                "sha256": "7a54ad7fc4bbeb64c5f7434bbbba09e3"}
+                "sha256": "84bfe862e1c3520267702c18229d933b"}
 
 
 def _sources_hash(names):
@@ -83,7 +83,7 @@ def algorithmic_pair_flops(system, table, r_pot):
 
 
 class Runner:
-    def __init__(self, system, table, mode="plain", skin=0.0):
+    def __init__(self, system, table, mode="plain", skin=0.0, per_atom=False):
         import torch
         from paper_2310_05279_amd import d3
         self.torch, self.d3 = torch, d3
@@ -97,14 +97,28 @@ class Runner:
                     "forces": torch.zeros((self.n, 3), dtype=torch.float64, device=self.dev),
                     "virial": torch.zeros((3, 3), dtype=torch.float64, device=self.dev),
                     "atom_energy": None}
+        # per-atom virials (Eq. 7) and heat currents (Eq. 8) at 300 K-like velocities
+        self.per_atom = per_atom
+        if per_atom:
+            self.out["atom_virial"] = torch.zeros((self.n, 3, 3), dtype=torch.float64,
+                                                  device=self.dev)
+            self.out["heat_current"] = torch.zeros((self.n, 3), dtype=torch.float64,
+                                                   device=self.dev)
+            rng = np.random.default_rng(300)
+            self.vel = torch.as_tensor(rng.normal(scale=0.01, size=(self.n, 3)), device=self.dev)
         self.stream = torch.cuda.current_stream()
 
     def step(self, rebuild=True):
         d3, c = self.d3, self.calc
         if rebuild:
             d3.d3_build_neighbors(c.ctx, c.pos, c.types, self.cell, self.pbc, self.stream)
-        d3.d3_energy_forces_virial(c.ctx, c.pos, self.out["energy"], self.out["forces"],
-                                   self.out["virial"], None, 0, self.stream)
+        if self.per_atom:
+            o = self.out
+            d3.d3_evaluate(c.ctx, c.pos, o["energy"], o["forces"], o["virial"], None,
+                           o["atom_virial"], self.vel, o["heat_current"], 0, self.stream)
+        else:
+            d3.d3_energy_forces_virial(c.ctx, c.pos, self.out["energy"], self.out["forces"],
+                                       self.out["virial"], None, 0, self.stream)
 
     def timed(self, steps, warmup, rebuild=True):
         torch = self.torch
@@ -267,6 +281,15 @@ def main():
                              "max_abs_dF_vs_plain": float(np.abs(fp - res_f).max()),
                              "abs_dE_per_atom_vs_plain": abs(ep - res_e) / n,
                              "max_abs_dW_vs_plain": float(np.abs(wp - res_w).max())}
+        # per-atom virial (Eq. 7) and heat current (Eq. 8) on top of the plain step
+        run = Runner(system, table, "plain", per_atom=True)
+        ms_a = run.timed(args.steps, args.warmup)
+        pha = run.phases(max(20, args.steps // 4))
+        fa = run.out["forces"].cpu().numpy()
+        run.close()
+        extra["plain_with_atom_virial"] = {
+            "atom_steps_per_s": n / (ms_a * 1e-3), "ms_per_step": ms_a, "phase_ms": pha,
+            "step_time_vs_plain": ms_a / ms, "forces_identical": bool(np.array_equal(fa, res_f))}
         # learned C6 surrogate: trained on 10^6 exact-labelled CN pairs over the
         # CN box [0, 99.9th percentile + 0.5]^2 of this cell, then timed
         from paper_2310_05279_amd import d3 as d3mod

@@ -38,8 +38,8 @@
  *    context must be ordered (same stream, or synchronised by the caller).
  *  - Stream capture (HIP graphs): once a build of the same (n, cell, pbc)
  *    and the same call in the same mode have completed on the context
- *    (so that every buffer exists), d3_build_neighbors,
- *    d3_coordination and d3_energy_forces_virial (n > 0, flags without
+ *    (so that every buffer exists), d3_build_neighbors, d3_coordination,
+ *    d3_energy_forces_virial and d3_evaluate (n > 0, flags without
  *    D3_AUTO_REBUILD, timing off) enqueue kernels only: no allocation,
  *    memset, copy or synchronisation, so they may be captured and the
  *    graph replayed on new positions written into the same buffers.
@@ -169,6 +169,33 @@ int d3_energy_forces_virial(d3_ctx *ctx, const double *pos, double *energy,
                             double *forces, double *virial,
                             double *atom_energy, uint32_t flags,
                             void *stream);
+
+/* Output pointers of d3_evaluate.  All are device memory in the caller's
+ * atom order; energy is required, every other pointer may be NULL. */
+typedef struct d3_outputs {
+    double *energy;       /* double[1]: E, Eq. 1 (eV) */
+    double *forces;       /* (n,3): exact negative gradient (eV/A) */
+    double *virial;       /* double[9] row-major: Eq. 7 summed over atoms (eV) */
+    double *atom_energy;  /* double[n]: site energies U_i, Eq. 2 (eV) */
+    double *atom_virial;  /* (n,9) row-major per atom: W_i of Eq. 7 (eV) */
+    const double *velocities; /* (n,3), any unit; read only for heat_current */
+    double *heat_current; /* (n,3): J_i = W_i v_i, Eq. 8 (eV x velocity unit) */
+} d3_outputs;
+
+/* d3_energy_forces_virial with the per-atom virial of Eq. 7 and the
+ * per-atom heat current of Eq. 8 as further optional outputs.  W_i is the
+ * share of atom i in the virial: every entry (i, j, T) of i contributes
+ * -1/2 [phi'(r) 1(r < R_pot) + (G_i + G_j) f'(r) 1(r < R_cn)] r (x) r / r
+ * (each pair's term split evenly between its atoms), so sum_i W_i equals
+ * the virial; for the direct part this is r_ij (x) dU_j/dr_ji as in Eq. 7.
+ * J_i = W_i v_i needs velocities.  With D3_ACCUMULATE every requested
+ * output is added to.  Requesting atom_virial or heat_current runs
+ * variants of the dispersion and chain passes that also sum six tensor
+ * components per atom; without them this call is d3_energy_forces_virial.
+ * Errors: as d3_energy_forces_virial; INVALID_ARG if out or out->energy
+ * is NULL or heat_current is given without velocities. */
+int d3_evaluate(d3_ctx *ctx, const double *pos, const d3_outputs *out,
+                uint32_t flags, void *stream);
 
 /* Synchronise the stream of the last call and report (then clear) the
  * conditions the device recorded: SPECIES, CAPACITY, STALE, or 0. */

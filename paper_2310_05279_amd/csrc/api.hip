@@ -578,12 +578,16 @@ int d3_coordination(d3_ctx* c, const double* pos, double* cn_out, void* stream)
     return D3_OK;
 }
 
-int d3_energy_forces_virial(d3_ctx* c, const double* pos, double* energy, double* forces,
-                            double* virial, double* atom_energy, uint32_t flags, void* stream)
+static int run_evaluate(d3_ctx* c, const double* pos, const d3_outputs& o, uint32_t flags,
+                        void* stream, const char* who)
 {
+    double* energy = o.energy;
+    double* virial = o.virial;
     if (!c) return fail(D3_ERR_INVALID_ARG, "ctx is NULL");
-    if (!c->built) return fail(D3_ERR_STATE, "d3_energy_forces_virial before d3_build_neighbors");
+    if (!c->built) return fail(D3_ERR_STATE, "%s before d3_build_neighbors", who);
     if (!energy) return fail(D3_ERR_INVALID_ARG, "energy is NULL");
+    if (o.heat_current && !o.velocities)
+        return fail(D3_ERR_INVALID_ARG, "heat_current needs velocities");
     if (c->n > 0 && !pos) return fail(D3_ERR_INVALID_ARG, "pos is NULL");
     if (flags & ~(D3_ACCUMULATE | D3_AUTO_REBUILD)) return fail(D3_ERR_INVALID_ARG, "unknown flags");
     hipStream_t s = (hipStream_t)stream;
@@ -612,8 +616,26 @@ int d3_energy_forces_virial(d3_ctx* c, const double* pos, double* energy, double
         }
     }
     const int mode = c->prm.mode;
-    D3CHK(evaluate(c, mode, energy, forces, virial, atom_energy, acc, s));
+    D3CHK(evaluate(c, mode, energy, o.forces, virial, o.atom_energy, o.atom_virial, o.velocities,
+                   o.heat_current, acc, s));
     return D3_OK;
+}
+
+int d3_energy_forces_virial(d3_ctx* c, const double* pos, double* energy, double* forces,
+                            double* virial, double* atom_energy, uint32_t flags, void* stream)
+{
+    d3_outputs o{};
+    o.energy = energy;
+    o.forces = forces;
+    o.virial = virial;
+    o.atom_energy = atom_energy;
+    return run_evaluate(c, pos, o, flags, stream, "d3_energy_forces_virial");
+}
+
+int d3_evaluate(d3_ctx* c, const double* pos, const d3_outputs* out, uint32_t flags, void* stream)
+{
+    if (!out) return fail(D3_ERR_INVALID_ARG, "out is NULL");
+    return run_evaluate(c, pos, *out, flags, stream, "d3_evaluate");
 }
 
 int d3_status(d3_ctx* c)
@@ -703,10 +725,17 @@ int rebuild_grow(d3_ctx* c, const double* pos, hipStream_t s)
 }
 
 int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial,
-             double* atom_energy, int acc, hipStream_t s)
+             double* atom_energy, double* atom_virial, const double* vel, double* heat_current,
+             int acc, hipStream_t s)
 {
     const int n = (int)c->n;
     const Geo& g = c->geo;
+    // per-atom virials: the direct part goes through Vp to the chain pass
+    double* Vp = nullptr;
+    if (atom_virial || heat_current) {
+        D3CHK(ensure(c->Vp, (size_t)(n > 0 ? n : 1) * 6 * sizeof(double)));
+        Vp = c->Vp.as<double>();
+    }
     int cn_mode = mode == D3_MODE_PREC_F32 ? D3_MODE_PREC_F32 : D3_MODE_PLAIN_F64;
     if (mode == D3_MODE_SURROGATE) {
         if (!c->sur || !c->sur->trained)
@@ -723,14 +752,14 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
     phase_mark(c, PH_PAIR, s);
     int na = 0;
     if (mode == D3_MODE_SURROGATE) {
-        D3CHK(surrogate_pair(c, sc, s, &na));
+        D3CHK(surrogate_pair(c, sc, Vp, s, &na));
     } else {
         na = launch_pair(mode, n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img,
                     g.img_bits, c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p,
                     c->d_tab.as<ElemTab>(), c->d_c6.as<double>(), c->d_pc.as<double4>(), sc,
                     c->w.as<double>(), c->wd.as<double>(), c->P.as<double>(), c->Pf.as<float>(),
                     c->Fp.as<double>(), c->U.as<double>(),
-                    c->G.as<double>(), c->vpart.as<double>(), s);
+                    c->G.as<double>(), Vp, c->vpart.as<double>(), s);
         HIPCHK(hipGetLastError());
     }
     phase_mark(c, PH_PAIR, s);
@@ -739,7 +768,8 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
                  c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img, g.img_bits,
                  c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, c->d_tab.as<ElemTab>(),
                  sc.rc2, c->G.as<double>(), c->Fp.as<double>(), c->U.as<double>(),
-                 c->perm.as<int>(), forces, atom_energy, acc, c->vpart2.as<double>(), s);
+                 c->perm.as<int>(), forces, atom_energy, Vp, vel, atom_virial, heat_current,
+                 acc, c->vpart2.as<double>(), s);
     HIPCHK(hipGetLastError());
     launch_final(na, c->vpart.as<double>(), nb, c->vpart2.as<double>(), energy, virial, acc, s);
     phase_mark(c, PH_CHAIN, s);

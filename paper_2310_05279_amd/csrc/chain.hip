@@ -1,8 +1,9 @@
 // The chain pass through the coordination numbers (the many-body part of
 // Eqs. 5-7): per entry within R_cn, F_i += (G_i + G_j) f'(r) r_vec / r and
 // the matching virial, with f the counting function of Eq. 4 and
-// G = dE/dn from the dispersion pass; then the total force is written in
-// the caller's atom order.  The energy (Eq. 1) and virial totals are
+// G = dE/dn from the dispersion pass; then the total force (and, if asked,
+// the per-atom virial and heat current of Eqs. 7-8) is written in the
+// caller's atom order.  The energy (Eq. 1) and virial totals are
 // summed afterwards from the workgroup partials of both passes in a fixed
 // order.
 #include "d3_device.h"
@@ -11,14 +12,19 @@ namespace d3 {
 
 constexpr int ROW = 16;  // lanes per atom: four atoms per wave, one per DPP row
 
-template <bool F32, bool IMG>
+// AV: also each atom's virial (Eq. 7): the chain part of its entries added
+// to the direct part Vp from the dispersion pass, written as a 3x3 tensor
+// in the caller's order, and if heat_current is set the heat current of
+// Eq. 8, J_i = W_i v_i, with v in the caller's order.
+template <bool F32, bool IMG, bool AV>
 __global__ void __launch_bounds__(BLOCK)
 k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_tab, int n_img,
         int img_bits, const uint32_t* __restrict__ list_c, const int* __restrict__ cnt_c,
         int cap_c, const ElemTab* __restrict__ tab, double rc2, const double* __restrict__ G,
         const double* __restrict__ Fp, const double* __restrict__ U, const int* __restrict__ perm,
-        double* __restrict__ forces, double* __restrict__ atom_energy, int accumulate,
-        double* __restrict__ part)
+        double* __restrict__ forces, double* __restrict__ atom_energy, const double* __restrict__ Vp,
+        const double* __restrict__ vel, double* __restrict__ atom_virial,
+        double* __restrict__ heat_current, int accumulate, double* __restrict__ part)
 {
     __shared__ double4 s_img[IMG ? IMG_LDS : 1];
     __shared__ double s_rcov[MAXELEM];
@@ -45,6 +51,7 @@ k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ im
         int mc = max(cnt, __shfl_xor(cnt, ROW, WAVE));
         mc = __builtin_amdgcn_readfirstlane(max(mc, __shfl_xor(mc, 2 * ROW, WAVE)));
         double fx = 0.0, fy = 0.0, fz = 0.0;
+        double av[6] = {0, 0, 0, 0, 0, 0};  // this atom's chain virial (AV only)
         for (int k0 = 0; k0 < mc; k0 += ROW) {
             const int k = k0 + rl;
             const uint32_t code = list_code(lc, k, cnt, cap_c);
@@ -80,6 +87,14 @@ k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ im
                 vir[3] += (double)(hy * y);
                 vir[4] += (double)(hy * zz);
                 vir[5] += (double)(h * zz * zz);
+                if constexpr (AV) {
+                    av[0] += (double)(hx * x);
+                    av[1] += (double)(hx * y);
+                    av[2] += (double)(hx * zz);
+                    av[3] += (double)(hy * y);
+                    av[4] += (double)(hy * zz);
+                    av[5] += (double)(h * zz * zz);
+                }
             } else {
                 const double q2 = in ? r2 : 1.0;
                 const double r = sqrt(q2);
@@ -90,11 +105,16 @@ k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ im
                 fy = fma(coef, dy, fy);
                 fz = fma(coef, dz, fz);
                 virial_add(vir, -0.5 * coef, dx, dy, dz);
+                if constexpr (AV) virial_add(av, -0.5 * coef, dx, dy, dz);
             }
         }
         fx = row_sum(fx);
         fy = row_sum(fy);
         fz = row_sum(fz);
+        if constexpr (AV) {
+#pragma unroll
+            for (int c = 0; c < 6; c++) av[c] = row_sum(av[c]);
+        }
         if (live && rl == 0) {
             const size_t o = (size_t)perm[i];
             const double f0 = Fp[3 * (size_t)i] + fx;
@@ -114,6 +134,27 @@ k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ im
             if (atom_energy) {
                 if (accumulate) atom_energy[o] += U[i];
                 else atom_energy[o] = U[i];
+            }
+            if constexpr (AV) {
+                double t[6];
+#pragma unroll
+                for (int c = 0; c < 6; c++) t[c] = Vp[6 * (size_t)i + c] + av[c];
+                // symmetric: xx xy xz yy yz zz
+                const double m[9] = {t[0], t[1], t[2], t[1], t[3], t[4], t[2], t[4], t[5]};
+                if (atom_virial) {
+                    double* wo = atom_virial + 9 * o;
+#pragma unroll
+                    for (int c = 0; c < 9; c++) wo[c] = accumulate ? wo[c] + m[c] : m[c];
+                }
+                if (heat_current) {
+                    const double v0 = vel[3 * o], v1 = vel[3 * o + 1], v2 = vel[3 * o + 2];
+                    const double j[3] = {m[0] * v0 + m[1] * v1 + m[2] * v2,
+                                         m[3] * v0 + m[4] * v1 + m[5] * v2,
+                                         m[6] * v0 + m[7] * v1 + m[8] * v2};
+                    double* jo = heat_current + 3 * o;
+#pragma unroll
+                    for (int c = 0; c < 3; c++) jo[c] = accumulate ? jo[c] + j[c] : j[c];
+                }
             }
         }
     }
@@ -199,25 +240,38 @@ int launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab, 
                  int img_bits, const uint32_t* list_c, const int* cnt_c, int cap_c,
                  const ElemTab* tab, double rc2, const double* G, const double* Fp,
                  const double* U, const int* perm, double* forces, double* atom_energy,
+                 const double* Vp, const double* vel, double* atom_virial, double* heat_current,
                  int accumulate, double* part, hipStream_t s)
 {
     if (n <= 0) return 0;
     const int groups = (n + WAVE / ROW - 1) / (WAVE / ROW);
     const bool lds = n_img <= IMG_LDS;
     int nblk = 0;
-#define D3_CHAIN(F, I)                                                                          \
+#define D3_CHAIN(F, I, A)                                                                       \
     {                                                                                           \
-        nblk = pass_blocks((const void*)&k_chain<F, I>, groups);                                \
-        hipLaunchKernelGGL((k_chain<F, I>), dim3(nblk), dim3(BLOCK), 0, s, n, pos_s, img_tab,   \
-                           n_img, img_bits, list_c, cnt_c, cap_c, tab, rc2, G, Fp, U, perm,     \
-                           forces, atom_energy, accumulate, part);                              \
+        nblk = pass_blocks((const void*)&k_chain<F, I, A>, groups);                             \
+        hipLaunchKernelGGL((k_chain<F, I, A>), dim3(nblk), dim3(BLOCK), 0, s, n, pos_s,         \
+                           img_tab, n_img, img_bits, list_c, cnt_c, cap_c, tab, rc2, G, Fp, U,  \
+                           perm, forces, atom_energy, Vp, vel, atom_virial, heat_current,      \
+                           accumulate, part);                                                   \
     }
-    if (mode == D3_MODE_PREC_F32) {
-        if (lds) D3_CHAIN(true, true)
-        else D3_CHAIN(true, false)
+    const bool prec = mode == D3_MODE_PREC_F32;
+    if (Vp) {
+        if (prec) {
+            if (lds) D3_CHAIN(true, true, true)
+            else D3_CHAIN(true, false, true)
+        } else {
+            if (lds) D3_CHAIN(false, true, true)
+            else D3_CHAIN(false, false, true)
+        }
     } else {
-        if (lds) D3_CHAIN(false, true)
-        else D3_CHAIN(false, false)
+        if (prec) {
+            if (lds) D3_CHAIN(true, true, false)
+            else D3_CHAIN(true, false, false)
+        } else {
+            if (lds) D3_CHAIN(false, true, false)
+            else D3_CHAIN(false, false, false)
+        }
     }
 #undef D3_CHAIN
     return nblk;

@@ -64,7 +64,7 @@ struct d3_ctx {
     d3::Buf list_p, cnt_p, list_c, cnt_c;
     int cap_p = 0, cap_c = 0;
     // per-atom results
-    d3::Buf cn, cnf, w, wd, P, Pf, G, Fp, U, vpart, vpart2;
+    d3::Buf cn, cnf, w, wd, P, Pf, G, Fp, U, Vp, vpart, vpart2;
     // status
     d3::Buf status, maxcnt, ticket;
     int* h_status = nullptr;
@@ -86,7 +86,7 @@ struct d3_ctx {
         return {&d_tab, &d_c6, &d_pc, &bin_of, &shift, &count, &bin_start,
                 &scan_tmp, &perm_tmp, &perm, &slab, &pos_s, &shift_s, &ref_s, &type_copy,
                 &img_tab, &list_p, &cnt_p, &list_c, &cnt_c, &cn, &cnf, &w, &wd, &P,
-                &Pf, &G, &Fp, &U, &vpart, &vpart2, &status, &maxcnt, &ticket, &md_scratch};
+                &Pf, &G, &Fp, &U, &Vp, &vpart, &vpart2, &status, &maxcnt, &ticket, &md_scratch};
     }
 };
 
@@ -98,7 +98,8 @@ int rebuild_grow(d3_ctx* c, const double* pos, hipStream_t s);
 int update_positions(d3_ctx* c, const double* pos, hipStream_t s);
 int coordination(d3_ctx* c, int mode, hipStream_t s);
 int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial,
-             double* atom_energy, int acc, hipStream_t s);
+             double* atom_energy, double* atom_virial, const double* vel, double* heat_current,
+             int acc, hipStream_t s);
 int read_status(d3_ctx* c, hipStream_t s, int* out);
 int status_code(int bits);
 int alloc_proj(d3_ctx* c, int mode);
@@ -110,6 +111,6 @@ int timing_flush(d3_ctx* c);
 
 // surrogate (mlp.hip)
 void surrogate_free(d3_ctx* c);
-int surrogate_pair(d3_ctx* c, const PairScal& sc, hipStream_t s, int* nblk);
+int surrogate_pair(d3_ctx* c, const PairScal& sc, double* Vp, hipStream_t s, int* nblk);
 
 }  // namespace d3

@@ -88,12 +88,13 @@ int launch_pair(int mode, int n, const double4* pos_s, const double4* img_tab, i
                  int img_bits, const uint32_t* list_p, const int* cnt_p, int cap_p,
                  const ElemTab* tab, const double* c6ref, const double4* pc, PairScal sc,
                  const double* w, const double* wd, const double* W, const float* Wf, double* Fp,
-                 double* U, double* G, double* part, hipStream_t s);
+                 double* U, double* G, double* Vp, double* part, hipStream_t s);
 int launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
                   int img_bits, const uint32_t* list_c, const int* cnt_c, int cap_c,
                   const ElemTab* tab, double rc2, const double* G, const double* Fp,
                   const double* U, const int* perm, double* forces, double* atom_energy,
-                  int accumulate, double* part, hipStream_t s);
+                  const double* Vp, const double* vel, double* atom_virial,
+                  double* heat_current, int accumulate, double* part, hipStream_t s);
 void launch_final(int na, const double* part_a, int nb, const double* part_b, double* energy,
                   double* virial, int accumulate, hipStream_t s);
 void launch_scatter_out(int n, const double* src, const int* perm, double* dst, hipStream_t s);

@@ -75,7 +75,9 @@ __device__ __forceinline__ void fetch(Nbr<F32>& nb, uint32_t code, int img_bits,
     }
 }
 
-template <bool F32, bool IMG>
+// AV: also the direct part of each atom's virial (Eq. 7), the six
+// components of sum over its entries of -1/2 phi'(r) r (x) r / r, to Vp.
+template <bool F32, bool IMG, bool AV>
 __global__ void __launch_bounds__(BLOCK)
 k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_tab, int n_img,
        int img_bits, const uint32_t* __restrict__ list_p, const int* __restrict__ cnt_p, int cap_p,
@@ -83,7 +85,7 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
        const double4* __restrict__ pc, PairScal sc, const double* __restrict__ w,
        const double* __restrict__ wd, const double* __restrict__ W, const float* __restrict__ Wf,
        double* __restrict__ Fp, double* __restrict__ U, double* __restrict__ G,
-       double* __restrict__ part)
+       double* __restrict__ Vp, double* __restrict__ part)
 {
     typedef typename std::conditional<F32, float, double>::type real;
     __shared__ double4 s_img[IMG ? IMG_LDS : 1];
@@ -141,6 +143,7 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
         Nbr<F32> nb_c;
         fetch<F32>(nb_c, code_c, img_bits, pos_s, W, Wf);
         double fx = 0.0, fy = 0.0, fz = 0.0, ue = 0.0, g = 0.0;
+        double av[6] = {0, 0, 0, 0, 0, 0};  // this atom's virial (AV only)
         for (int k0 = 0; k0 < cnt; k0 += WAVE) {
             const int k = k0 + lane;
             // prefetch: codes two chunks ahead, neighbour data one chunk ahead
@@ -181,6 +184,7 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
                 fy = fma(dphi_r, dy, fy);
                 fz = fma(dphi_r, dz, fz);
                 virial_add(vir, -0.5 * dphi_r, dx, dy, dz);
+                if constexpr (AV) virial_add(av, -0.5 * dphi_r, dx, dy, dz);
             } else {
                 const float wj[MAXREF] = {nb_c.w03.x, nb_c.w03.y, nb_c.w03.z, nb_c.w03.w, nb_c.w4};
                 float c6 = 0.0f, dc6 = 0.0f;
@@ -211,12 +215,31 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
                 vir[3] += (double)(hy * y);
                 vir[4] += (double)(hy * zz);
                 vir[5] += (double)(h * zz * zz);
+                if constexpr (AV) {
+                    av[0] += (double)(hx * x);
+                    av[1] += (double)(hx * y);
+                    av[2] += (double)(hx * zz);
+                    av[3] += (double)(hy * y);
+                    av[4] += (double)(hy * zz);
+                    av[5] += (double)(h * zz * zz);
+                }
             }
             code_c = code_n;
             code_n = code_nn;
             nb_c = nb_n;
         }
-        {
+        if constexpr (AV) {
+            double t[11] = {fx, fy, fz, ue, g, av[0], av[1], av[2], av[3], av[4], av[5]};
+            wave_sums(t);
+            fx = t[0];
+            fy = t[1];
+            fz = t[2];
+            ue = t[3];
+            g = t[4];
+            if (lane == 0)
+#pragma unroll
+                for (int c = 0; c < 6; c++) Vp[6 * (size_t)i + c] = t[5 + c];
+        } else {
             double t[5] = {fx, fy, fz, ue, g};
             wave_sums(t);
             fx = t[0];
@@ -245,24 +268,35 @@ int launch_pair(int mode, int n, const double4* pos_s, const double4* img_tab, i
                 int img_bits, const uint32_t* list_p, const int* cnt_p, int cap_p,
                 const ElemTab* tab, const double* c6ref, const double4* pc, PairScal sc,
                 const double* w, const double* wd, const double* W, const float* Wf, double* Fp,
-                double* U, double* G, double* part, hipStream_t s)
+                double* U, double* G, double* Vp, double* part, hipStream_t s)
 {
     if (n <= 0) return 0;
     const bool lds = n_img <= IMG_LDS;
     int nblk = 0;
-#define D3_PAIR(F, I)                                                                           \
+#define D3_PAIR(F, I, A)                                                                        \
     {                                                                                           \
-        nblk = pass_blocks((const void*)&k_pair<F, I>, n);                                      \
-        hipLaunchKernelGGL((k_pair<F, I>), dim3(nblk), dim3(BLOCK), 0, s, n, pos_s, img_tab,    \
+        nblk = pass_blocks((const void*)&k_pair<F, I, A>, n);                                   \
+        hipLaunchKernelGGL((k_pair<F, I, A>), dim3(nblk), dim3(BLOCK), 0, s, n, pos_s, img_tab, \
                            n_img, img_bits, list_p, cnt_p, cap_p, tab, c6ref, pc, sc, w, wd, W, \
-                           Wf, Fp, U, G, part);                                                 \
+                           Wf, Fp, U, G, Vp, part);                                             \
     }
-    if (mode == D3_MODE_PREC_F32) {
-        if (lds) D3_PAIR(true, true)
-        else D3_PAIR(true, false)
+    const bool prec = mode == D3_MODE_PREC_F32;
+    if (Vp) {
+        if (prec) {
+            if (lds) D3_PAIR(true, true, true)
+            else D3_PAIR(true, false, true)
+        } else {
+            if (lds) D3_PAIR(false, true, true)
+            else D3_PAIR(false, false, true)
+        }
     } else {
-        if (lds) D3_PAIR(false, true)
-        else D3_PAIR(false, false)
+        if (prec) {
+            if (lds) D3_PAIR(true, true, false)
+            else D3_PAIR(true, false, false)
+        } else {
+            if (lds) D3_PAIR(false, true, false)
+            else D3_PAIR(false, false, false)
+        }
     }
 #undef D3_PAIR
     return nblk;

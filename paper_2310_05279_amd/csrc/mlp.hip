@@ -598,14 +598,17 @@ k_sur_eval(int m, const int32_t* __restrict__ ei, const int32_t* __restrict__ ej
 // accumulation), with C6 and dC6/dn_i from the surrogate.  Each atom's
 // list is first sorted by the neighbour's element in LDS, so every 64-entry
 // step uses a single network.
-template <bool IMG>
+// AV: also the direct part of each atom's virial (Eq. 7) to Vp, as in the
+// exact dispersion pass.
+template <bool IMG, bool AV>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3)))
 k_pair_sur(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_tab,
            int n_img, int img_bits, const uint32_t* __restrict__ list_p,
            const int* __restrict__ cnt_p, int cap_p, const ElemTab* __restrict__ tab,
            const double* __restrict__ c6ref, const double4* __restrict__ pc, PairScal sc,
            const double* __restrict__ cn, SurView sv, double* __restrict__ Fp,
-           double* __restrict__ U, double* __restrict__ G, double* __restrict__ part)
+           double* __restrict__ U, double* __restrict__ G, double* __restrict__ Vp,
+           double* __restrict__ part)
 {
     __shared__ double4 s_img[IMG ? IMG_LDS : 1];
     __shared__ double4 s_pc[SUR_ELEM * SUR_ELEM];
@@ -634,6 +637,7 @@ k_pair_sur(int n, const double4* __restrict__ pos_s, const double4* __restrict__
         const int cnt_all = min(cnt_p[i], cap_p);
         const uint32_t* row = list_p + (size_t)i * cap_p;
         double fx = 0.0, fy = 0.0, fz = 0.0, ue = 0.0, g = 0.0;
+        double av[6] = {0, 0, 0, 0, 0, 0};  // this atom's virial (AV only)
         // the list is taken in chunks of at most SUR_CAP entries
         for (int c0 = 0; c0 < cnt_all; c0 += SUR_CAP) {
             const int cnt = min(cnt_all - c0, SUR_CAP);
@@ -746,12 +750,31 @@ k_pair_sur(int n, const double4* __restrict__ pos_s, const double4* __restrict__
                     vir[3] += (double)(hy * yv);
                     vir[4] += (double)(hy * zz);
                     vir[5] += (double)(hh * zz * zz);
+                    if constexpr (AV) {
+                        av[0] += (double)(hx * x);
+                        av[1] += (double)(hx * yv);
+                        av[2] += (double)(hx * zz);
+                        av[3] += (double)(hy * yv);
+                        av[4] += (double)(hy * zz);
+                        av[5] += (double)(hh * zz * zz);
+                    }
                 }
                 base += cf;
             }
             __builtin_amdgcn_wave_barrier();  // LDS rows are reused by the next chunk
         }
-        {
+        if constexpr (AV) {
+            double t[11] = {fx, fy, fz, ue, g, av[0], av[1], av[2], av[3], av[4], av[5]};
+            wave_sums(t);
+            fx = t[0];
+            fy = t[1];
+            fz = t[2];
+            ue = t[3];
+            g = t[4];
+            if (lane == 0)
+#pragma unroll
+                for (int c = 0; c < 6; c++) Vp[6 * (size_t)i + c] = t[5 + c];
+        } else {
             double t[5] = {fx, fy, fz, ue, g};
             wave_sums(t);
             fx = t[0];
@@ -872,7 +895,7 @@ static SurView view(const d3_ctx* c)
     return v;
 }
 
-int surrogate_pair(d3_ctx* c, const PairScal& sc, hipStream_t st, int* nblk)
+int surrogate_pair(d3_ctx* c, const PairScal& sc, double* Vp, hipStream_t st, int* nblk)
 {
     *nblk = 0;
     if (!c->sur || !c->sur->trained)
@@ -882,23 +905,24 @@ int surrogate_pair(d3_ctx* c, const PairScal& sc, hipStream_t st, int* nblk)
     const int n = (int)c->n;
     if (n <= 0) return D3_OK;
     const Geo& g = c->geo;
-    const dim3 block(BLOCK);
-    if (g.n_img <= IMG_LDS)
-        hipLaunchKernelGGL((k_pair_sur<true>),
-                           dim3(*nblk = pass_blocks((const void*)&k_pair_sur<true>, n)), block, 0, st, n, c->pos_s.as<double4>(),
-                           c->img_tab.as<double4>(), g.n_img, g.img_bits, c->list_p.as<uint32_t>(),
-                           c->cnt_p.as<int>(), c->cap_p, c->d_tab.as<ElemTab>(),
-                           c->d_c6.as<double>(), c->d_pc.as<double4>(), sc, c->cn.as<double>(),
-                           view(c), c->Fp.as<double>(), c->U.as<double>(), c->G.as<double>(),
-                           c->vpart.as<double>());
-    else
-        hipLaunchKernelGGL((k_pair_sur<false>),
-                           dim3(*nblk = pass_blocks((const void*)&k_pair_sur<false>, n)), block, 0, st, n, c->pos_s.as<double4>(),
-                           c->img_tab.as<double4>(), g.n_img, g.img_bits, c->list_p.as<uint32_t>(),
-                           c->cnt_p.as<int>(), c->cap_p, c->d_tab.as<ElemTab>(),
-                           c->d_c6.as<double>(), c->d_pc.as<double4>(), sc, c->cn.as<double>(),
-                           view(c), c->Fp.as<double>(), c->U.as<double>(), c->G.as<double>(),
-                           c->vpart.as<double>());
+#define D3_SUR(I, A)                                                                           \
+    hipLaunchKernelGGL((k_pair_sur<I, A>),                                                     \
+                       dim3(*nblk = pass_blocks((const void*)&k_pair_sur<I, A>, n)),           \
+                       dim3(BLOCK), 0, st, n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), \
+                       g.n_img, g.img_bits, c->list_p.as<uint32_t>(), c->cnt_p.as<int>(),      \
+                       c->cap_p, c->d_tab.as<ElemTab>(), c->d_c6.as<double>(),                 \
+                       c->d_pc.as<double4>(), sc, c->cn.as<double>(), view(c),                 \
+                       c->Fp.as<double>(), c->U.as<double>(), c->G.as<double>(), Vp,           \
+                       c->vpart.as<double>())
+    const bool lds = g.n_img <= IMG_LDS;
+    if (Vp) {
+        if (lds) D3_SUR(true, true);
+        else D3_SUR(false, true);
+    } else {
+        if (lds) D3_SUR(true, false);
+        else D3_SUR(false, false);
+    }
+#undef D3_SUR
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_pair_sur");
     return D3_OK;

@@ -62,6 +62,12 @@ class d3_train_cfg(ctypes.Structure):
                 ("cn_hi", _c_d)]
 
 
+class d3_outputs(ctypes.Structure):
+    _fields_ = [("energy", _vp), ("forces", _vp), ("virial", _vp),
+                ("atom_energy", _vp), ("atom_virial", _vp), ("velocities", _vp),
+                ("heat_current", _vp)]
+
+
 class D3Error(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("d3 error %d: %s" % (code, msg))
@@ -77,6 +83,7 @@ _SIGS = {
     "d3_build_neighbors": (_c_i32, [_vp, _c_i64, _vp, _vp, _vp, _vp, _vp]),
     "d3_coordination": (_c_i32, [_vp, _vp, _vp, _vp]),
     "d3_energy_forces_virial": (_c_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _c_u32, _vp]),
+    "d3_evaluate": (_c_i32, [_vp, _vp, ctypes.POINTER(d3_outputs), _c_u32, _vp]),
     "d3_status": (_c_i32, [_vp]),
     "d3_list_stats": (_c_i32, [_vp, _vp]),
     "d3_set_timing": (_c_i32, [_vp, _c_i32]),
@@ -186,6 +193,15 @@ def d3_energy_forces_virial(ctx, pos, energy, forces=None, virial=None,
     _check(lib().d3_energy_forces_virial(ctx, _ptr(pos), _ptr(energy), _ptr(forces),
                                          _ptr(virial), _ptr(atom_energy), int(flags),
                                          _stream(stream)))
+
+
+def d3_evaluate(ctx, pos, energy, forces=None, virial=None, atom_energy=None,
+                atom_virial=None, velocities=None, heat_current=None, flags=0, stream=None):
+    def p(t):
+        return t.data_ptr() if t is not None else None
+    out = d3_outputs(p(energy), p(forces), p(virial), p(atom_energy), p(atom_virial),
+                     p(velocities), p(heat_current))
+    _check(lib().d3_evaluate(ctx, _ptr(pos), ctypes.byref(out), int(flags), _stream(stream)))
 
 
 def d3_status(ctx):
@@ -309,7 +325,11 @@ class D3:
         self.n = int(self.pos.shape[0])
         d3_build_neighbors(self.ctx, self.pos, self.types, cell, pbc, stream)
 
-    def compute(self, pos=None, atom_energy=True, flags=0, stream=None, out=None):
+    def compute(self, pos=None, atom_energy=True, flags=0, stream=None, out=None,
+                atom_virial=False, velocities=None):
+        """Energy, forces, virial and site energies; with atom_virial=True also
+        the per-atom virials (n,3,3), and given velocities (n,3) also the
+        per-atom heat currents (n,3)."""
         t = self.torch
         p = self.pos if pos is None else self._dev(pos, t.float64)
         if out is None:
@@ -318,8 +338,18 @@ class D3:
                    "virial": t.zeros((3, 3), dtype=t.float64, device=self.dev),
                    "atom_energy": (t.zeros(self.n, dtype=t.float64, device=self.dev)
                                    if atom_energy else None)}
-        d3_energy_forces_virial(self.ctx, p, out["energy"], out["forces"], out["virial"],
-                                out["atom_energy"], flags, stream)
+            if atom_virial:
+                out["atom_virial"] = t.zeros((self.n, 3, 3), dtype=t.float64, device=self.dev)
+            if velocities is not None:
+                out["heat_current"] = t.zeros((self.n, 3), dtype=t.float64, device=self.dev)
+        v = None if velocities is None else self._dev(velocities, t.float64)
+        if out.get("atom_virial") is None and out.get("heat_current") is None:
+            d3_energy_forces_virial(self.ctx, p, out["energy"], out["forces"], out["virial"],
+                                    out["atom_energy"], flags, stream)
+        else:
+            d3_evaluate(self.ctx, p, out["energy"], out["forces"], out["virial"],
+                        out["atom_energy"], out.get("atom_virial"), v, out.get("heat_current"),
+                        flags, stream)
         return out
 
     def coordination(self, pos=None, stream=None):

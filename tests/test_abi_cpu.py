@@ -82,6 +82,9 @@ def test_null_context_is_rejected_everywhere():
     assert L.d3_energy_forces_virial(None, None, None, None, None, None, 0, None) == \
         d3.D3_ERR_INVALID_ARG
     assert L.d3_status(None) == d3.D3_ERR_INVALID_ARG
+    assert L.d3_evaluate(None, None, None, 0, None) == d3.D3_ERR_INVALID_ARG
+    out = d3.d3_outputs()
+    assert L.d3_evaluate(None, None, ctypes.byref(out), 0, None) == d3.D3_ERR_INVALID_ARG
     assert L.d3_set_mode(None, 0) == d3.D3_ERR_INVALID_ARG
     assert L.d3_list_stats(None, None) == d3.D3_ERR_INVALID_ARG
     L.d3_destroy(None)  # accepted
