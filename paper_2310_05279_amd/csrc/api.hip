@@ -83,7 +83,8 @@ static void inv3(const double* m, double* o)
 }
 
 // Bin layout for list cutoff rlist: nb_k bins along lattice vector k,
-// each at least rlist / BIN_DIV wide (measured between lattice planes),
+// each about rlist / BIN_DIV wide or, for long cutoffs, the width that
+// holds BIN_ATOMS atoms (measured between lattice planes),
 // stencil reach ceil(rlist / width) bins, and the image translations the
 // stencil can reach on periodic axes.
 int make_geo(const double* cell, const int32_t* pbc, double rlist, int64_t n,
@@ -102,7 +103,14 @@ int make_geo(const double* cell, const int32_t* pbc, double rlist, int64_t n,
     std::memcpy(g.H, cell, sizeof(g.H));
     inv3(cell, g.Hinv);
     const double vol = std::fabs(det);
-    const double target = rlist / BIN_DIV;
+    // bins at least rlist / BIN_DIV wide; for a long cutoff, narrower bins
+    // that hold about BIN_ATOMS atoms at the cell's mean density (a deeper
+    // stencil of small bins keeps one bin per wave, with enough bins to
+    // fill the chip), but never narrower than rlist / MAX_REACH
+    double target = rlist / BIN_DIV;
+    if (n > 0)
+        target = std::min(target, std::max(std::cbrt(BIN_ATOMS * vol / (double)n),
+                                           rlist / MAX_REACH));
     double h[3];
     long nb[3];
     for (int k = 0; k < 3; k++) {

@@ -9,10 +9,11 @@
 // fastest along the first lattice vector, so one stencil row of bins is one
 // contiguous range of sorted atoms.
 //
-// Bins are at least a third of the list cutoff wide, so the stencil is 7
-// bins along each axis.  One wave builds the lists of all atoms of one bin
-// (see k_list); the bins are split between the XCDs in slabs that hold
-// equal shares of the atoms.
+// Bins are a third of the list cutoff wide (a 7-bin stencil along each
+// axis) or, for long cutoffs, narrow enough to hold a few atoms at the mean
+// density (a deeper stencil).  One wave builds the lists of all atoms of
+// one bin (see k_list); the bins are split between the XCDs in slabs that
+// hold equal shares of the atoms.
 #include "d3_device.h"
 
 namespace d3 {

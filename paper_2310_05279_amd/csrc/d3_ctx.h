@@ -9,7 +9,9 @@
 
 namespace d3 {
 
-constexpr double BIN_DIV = 3.0;  // bins per list cutoff along each axis
+constexpr double BIN_DIV = 3.0;     // bins per list cutoff along each axis (at most)
+constexpr double BIN_ATOMS = 2.6;   // mean atoms per bin for long cutoffs
+constexpr double MAX_REACH = 16.0;  // deepest stencil reach that narrower bins may give
 
 struct Buf {
     void* p = nullptr;

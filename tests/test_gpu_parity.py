@@ -141,9 +141,8 @@ def test_twelve_element_table():
 
 def test_dense_cell_long_cutoffs():
     """R_pot = 30 A and R_cn = 10 A on a dense 1 500-atom cell smaller than
-    the cutoff: the list build's bins then hold ~190 atoms (several groups
-    of 64 per wave), lists exceed 9 000 entries and images reach two cells
-    out."""
+    the cutoff: lists exceed 9 000 entries, images reach two cells out and
+    the list build's stencil reaches 10 bins each way."""
     m = synth.mof_like(1500, density=0.08, seed=14)
     prm = dict(r_pot=30.0, r_cn=10.0)
     ref = R.d3(m["pos"], m["types"], m["cell"], m["pbc"], TAB, **prm)
@@ -151,6 +150,25 @@ def test_dense_cell_long_cutoffs():
     print("dense: list stats %s" % gpu["stats"], flush=True)
     assert gpu["stats"]["max_pot"] > 8000
     compare(gpu, ref, 1500, label="dense")
+
+
+def test_dense_block_in_vacuum_large_bins():
+    """The dense 1 500-atom block in the middle of an 84 A periodic cube:
+    the mean density is low, so the list build keeps bins of R_list / 3 =
+    10 A, and the block's bins hold ~80 atoms each (two groups of 64 per
+    wave)."""
+    b = synth.mof_like(1500, density=0.08, seed=14)
+    side = b["cell"][0, 0]
+    L = 84.0
+    pos = np.mod(b["pos"], side) + 0.5 * (L - side)
+    s = {"pos": pos, "types": b["types"], "cell": np.diag([L, L, L]),
+         "pbc": np.array([1, 1, 1], np.int32)}
+    prm = dict(r_pot=30.0, r_cn=10.0)
+    ref = R.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB, **prm)
+    gpu = run_gpu(s, prm=prm)
+    print("block: list stats %s" % gpu["stats"], flush=True)
+    assert gpu["stats"]["bins"] == 512
+    compare(gpu, ref, 1500, label="block")
 
 
 def test_mof_24000_plain_config2():
