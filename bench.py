@@ -83,12 +83,12 @@ def algorithmic_pair_flops(system, table, r_pot):
 
 
 class Runner:
-    def __init__(self, system, table, mode="plain", skin=0.0, per_atom=False):
+    def __init__(self, system, table, mode="plain", skin=0.0, per_atom=False, **prm):
         import torch
         from paper_2310_05279_amd import d3
         self.torch, self.d3 = torch, d3
         self.dev = torch.device("cuda", 0)
-        self.calc = d3.D3(table, mode=mode, skin=skin)
+        self.calc = d3.D3(table, mode=mode, skin=skin, **prm)
         self.calc.build(system["pos"], system["types"], system["cell"], system["pbc"])
         self.cell = np.ascontiguousarray(system["cell"], dtype=np.float64)
         self.pbc = np.ascontiguousarray(system["pbc"], dtype=np.int32)
@@ -336,6 +336,26 @@ def main():
                  ("plain", "prec"))):
             extra[name] = forms(big, steps, modes)
             print("[bench] %s %s" % (name, json.dumps(extra[name])), file=sys.stderr, flush=True)
+
+        # long cutoffs on the 24 000-atom cell, R_cn = R_pot / 2: speed, and the
+        # force error of each cutoff against the 50 A result (plain FP64)
+        sweep, f50 = {}, None
+        for rp in (50.0, 40.0, 30.0, 20.0, 12.0):
+            run = Runner(system, table, "plain", r_pot=rp, r_cn=rp / 2)
+            msc = run.timed(10, 2)
+            phc = run.phases(5)
+            fc = run.out["forces"].cpu().numpy()
+            st = run.calc.stats()
+            run.close()
+            if f50 is None:
+                f50 = fc
+            sweep["%g" % rp] = {"r_cn": rp / 2, "atom_steps_per_s": n / (msc * 1e-3),
+                                "ms_per_step": msc, "phase_ms": phc,
+                                "mean_entries_pot": st["mean_pot"],
+                                "force_rmse_vs_50A": float(np.sqrt(((fc - f50) ** 2).mean())),
+                                "force_maxerr_vs_50A": float(np.abs(fc - f50).max())}
+        extra["cutoff_sweep_mof24000"] = sweep
+        print("[bench] cutoff sweep %s" % json.dumps(sweep), file=sys.stderr, flush=True)
 
         # velocity-Verlet NVE on the 10^6-atom cell: 300 K Maxwell start, 1 fs,
         # lists with a 1 A skin rebuilt when an atom moved more than 0.5 A

@@ -82,13 +82,107 @@ static void inv3(const double* m, double* o)
     o[8] = (m[0] * m[4] - m[1] * m[3]) / det;
 }
 
+// Squared smallest distance between the points of two bins whose indices
+// differ by d: the minimum of |sum_k t_k e_k|^2 over t_k in [d_k - 1,
+// d_k + 1], with e_k the bin edge vectors (lattice vector k / nb_k).  Along
+// an open axis t_k is free, because atoms outside the cell join the edge
+// bins.  The function is convex in t, so its minimum is one of the
+// stationary points of the 27 choices (free, lower bound, upper bound) per
+// axis; a free coordinate is clamped into its interval, which only gives a
+// feasible point (never a value below the minimum).
+static double bin_gap2(const double G[3][3], const int d[3], const int* pbc)
+{
+    double best = INFINITY;
+    for (int code = 0; code < 27; code++) {
+        const int mode[3] = {code % 3, (code / 3) % 3, code / 9};  // 0 free, 1 low, 2 high
+        double t[3] = {0.0, 0.0, 0.0};
+        int fr[3], nf = 0;
+        bool ok = true;
+        for (int k = 0; k < 3; k++) {
+            if (mode[k] == 0) fr[nf++] = k;
+            else if (!pbc[k]) ok = false;
+            else t[k] = d[k] + (mode[k] == 1 ? -1.0 : 1.0);
+        }
+        if (!ok) continue;
+        // G_FF t_F = -G_F,fixed t_fixed
+        double b[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < nf; a++)
+            for (int k = 0; k < 3; k++)
+                if (mode[k] != 0) b[a] -= G[fr[a]][k] * t[k];
+        if (nf == 1) {
+            t[fr[0]] = b[0] / G[fr[0]][fr[0]];
+        } else if (nf == 2) {
+            const double a00 = G[fr[0]][fr[0]], a01 = G[fr[0]][fr[1]], a11 = G[fr[1]][fr[1]];
+            const double det = a00 * a11 - a01 * a01;
+            t[fr[0]] = (b[0] * a11 - a01 * b[1]) / det;
+            t[fr[1]] = (a00 * b[1] - a01 * b[0]) / det;
+        }  // nf == 3: the unconstrained minimum t = 0
+        for (int a = 0; a < nf; a++) {
+            const int k = fr[a];
+            if (pbc[k]) t[k] = std::min(std::max(t[k], d[k] - 1.0), d[k] + 1.0);
+        }
+        double q = 0.0;
+        for (int k = 0; k < 3; k++)
+            for (int l = 0; l < 3; l++) q += t[k] * G[k][l] * t[l];
+        best = std::min(best, q);
+    }
+    return std::max(best, 0.0);
+}
+
+// Stencil row table of deep stencils (reach >= ROW_TABLE_REACH): for every
+// row offset (d1, d2) the range of d0 whose bins can hold a pair within
+// rlist (an interval, the gap being convex in d), the rows that can hold a
+// pair within rcn first.  Left empty (every row of the full stencil, as
+// computed in the kernel) for shallow stencils and for stencils too large
+// for a table.
+static void make_rows(const double* cell, Geo& g, double rlist, double rcn,
+                      std::vector<RowSpan>& rows)
+{
+    rows.clear();
+    g.nrows = g.ncnrows = 0;
+    const int rmax = std::max(g.reach[0], std::max(g.reach[1], g.reach[2]));
+    const long n0 = 2L * g.reach[0] + 1, n1 = 2L * g.reach[1] + 1, n2 = 2L * g.reach[2] + 1;
+    if (rmax < ROW_TABLE_REACH || n1 * n2 > MAX_ROW_TAB || n0 * n1 * n2 > (1L << 18)) return;
+    double e[3][3], G[3][3];
+    for (int k = 0; k < 3; k++)
+        for (int m = 0; m < 3; m++) e[k][m] = cell[3 * k + m] / g.nb[k];
+    for (int k = 0; k < 3; k++)
+        for (int l = 0; l < 3; l++) G[k][l] = e[k][0] * e[l][0] + e[k][1] * e[l][1] + e[k][2] * e[l][2];
+    // keep a bin when its gap is within the cutoff, with a relative margin
+    // far above the rounding of binning and wrapping
+    const double lim = rlist * rlist * (1.0 + 1e-9) + 1e-12;
+    const double limc = rcn * rcn * (1.0 + 1e-9) + 1e-12;
+    std::vector<RowSpan> cn_rows, far_rows;
+    for (int d2 = -g.reach[2]; d2 <= g.reach[2]; d2++)
+        for (int d1 = -g.reach[1]; d1 <= g.reach[1]; d1++) {
+            int lo = INT32_MAX, hi = INT32_MIN;
+            bool cn = false;
+            for (int d0 = -g.reach[0]; d0 <= g.reach[0]; d0++) {
+                const int d[3] = {d0, d1, d2};
+                const double q = bin_gap2(G, d, g.pbc);
+                if (q <= lim) {
+                    lo = std::min(lo, d0);
+                    hi = std::max(hi, d0);
+                }
+                if (q <= limc) cn = true;
+            }
+            if (lo > hi) continue;
+            (cn ? cn_rows : far_rows).push_back(RowSpan{d1, d2, lo, hi});
+        }
+    rows = cn_rows;
+    rows.insert(rows.end(), far_rows.begin(), far_rows.end());
+    g.nrows = (int)rows.size();
+    g.ncnrows = (int)cn_rows.size();
+}
+
 // Bin layout for list cutoff rlist: nb_k bins along lattice vector k,
 // each about rlist / BIN_DIV wide or, for long cutoffs, the width that
 // holds BIN_ATOMS atoms (measured between lattice planes),
-// stencil reach ceil(rlist / width) bins, and the image translations the
-// stencil can reach on periodic axes.
-int make_geo(const double* cell, const int32_t* pbc, double rlist, int64_t n,
-             Geo& g, std::vector<double4>& imgs)
+// stencil reach ceil(rlist / width) bins, the image translations the
+// stencil can reach on periodic axes, and the row table of a deep stencil
+// (rcn: the shorter list cutoff).
+int make_geo(const double* cell, const int32_t* pbc, double rlist, double rcn, int64_t n,
+             Geo& g, std::vector<double4>& imgs, std::vector<RowSpan>& rows)
 {
     double la[3];
     for (int k = 0; k < 3; k++)
@@ -159,6 +253,7 @@ int make_geo(const double* cell, const int32_t* pbc, double rlist, int64_t n,
                     T[m] = t0 * cell[m] + t1 * cell[3 + m] + t2 * cell[6 + m];
                 imgs[c++] = make_double4(T[0], T[1], T[2], 0.0);
             }
+    make_rows(cell, g, rlist, rcn, rows);
     return D3_OK;
 }
 
@@ -330,7 +425,7 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
     const double rp = c->prm.r_pot + c->prm.skin, rcn = c->prm.r_cn + c->prm.skin;
     if (size_lists) {
         launch_list(n, c->pos_s.as<double4>(), c->bin_start.as<int>(), c->slab.as<int>(), g,
-                    c->img_tab.as<double4>(),
+                    c->row_tab.as<RowSpan>(), c->img_tab.as<double4>(),
                     rp * rp, rcn * rcn, nullptr, c->cnt_p.as<int>(), 0, nullptr,
                     c->cnt_c.as<int>(), 0, 1, c->status.as<int>(), s);
         HIPCHK(hipGetLastError());
@@ -346,7 +441,7 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
         D3CHK(ensure(c->list_c, N * c->cap_c * sizeof(uint32_t)));
     }
     launch_list(n, c->pos_s.as<double4>(), c->bin_start.as<int>(), c->slab.as<int>(), g,
-                c->img_tab.as<double4>(),
+                c->row_tab.as<RowSpan>(), c->img_tab.as<double4>(),
                 rp * rp, rcn * rcn, c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p,
                 c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, 0, c->status.as<int>(), s);
     HIPCHK(hipGetLastError());
@@ -379,8 +474,9 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
     if (!same) {
         Geo g;
         std::vector<double4> imgs;
+        std::vector<RowSpan> rows;
         const double rlist = std::max(c->prm.r_pot, c->prm.r_cn) + c->prm.skin;
-        D3CHK(make_geo(cell, pbc, rlist, n, g, imgs));
+        D3CHK(make_geo(cell, pbc, rlist, c->prm.r_cn + c->prm.skin, n, g, imgs, rows));
         c->n = n;
         c->geo = g;
         std::memcpy(c->cell, cell, sizeof(c->cell));
@@ -393,6 +489,10 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
         D3CHK(ensure(c->img_tab, imgs.size() * sizeof(double4)));
         HIPCHK(hipMemcpyAsync(c->img_tab.p, imgs.data(), imgs.size() * sizeof(double4),
                               hipMemcpyHostToDevice, s));
+        D3CHK(ensure(c->row_tab, std::max<size_t>(rows.size(), 1) * sizeof(RowSpan)));
+        if (!rows.empty())
+            HIPCHK(hipMemcpyAsync(c->row_tab.p, rows.data(), rows.size() * sizeof(RowSpan),
+                                  hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
         c->built = false;
     }

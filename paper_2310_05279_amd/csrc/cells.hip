@@ -259,6 +259,7 @@ k_update(int n, const double* __restrict__ pos, const int* __restrict__ perm,
 }
 
 constexpr int LIST_AHEAD = 4;  // candidate steps whose loads are in flight together
+constexpr int ROW_LDS = 1024;  // stencil rows of the row table held in LDS
 
 // number of set bits of m below this lane
 __device__ __forceinline__ int lanes_below(unsigned long long m)
@@ -281,31 +282,37 @@ __device__ __forceinline__ int wave_incl_scan(int v)
 
 // One wave builds the lists of all atoms of one bin.  The bin's stencil is
 // cut into segments, one per stencil row and periodic image; each segment is
-// one contiguous range of sorted atoms.  Lanes take the segments' candidates
+// one contiguous range of sorted atoms.  TABLE (deep stencils of long
+// cutoffs): the rows come from a host-made table that drops the bins lying
+// wholly beyond the cutoff and puts the rows within R_cn reach first, so
+// the later candidates skip the R_cn test.  Lanes take the segments' candidates
 // densely packed, 64 per step (a lane finds its segment by a binary search
 // over the segment offsets held by the lanes), load each candidate once, and
 // test it in FP64 against every atom of the bin in turn; hits are compacted
 // with a ballot into the atom's row.  The test is the same FP64 arithmetic
 // as the passes, with a 1e-12 relative widening so that no pair a pass would
 // accept is missed; the passes make the exact decision.  COUNT: count only.
-template <bool IMG, bool COUNT>
+template <bool IMG, bool COUNT, bool TABLE>
 __global__ void __launch_bounds__(BLOCK)
 k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
-       const int* __restrict__ slab, Geo g,
+       const int* __restrict__ slab, Geo g, const RowSpan* __restrict__ row_tab,
        const double4* __restrict__ img_tab, double rp2, double rc2,
        uint32_t* __restrict__ list_p, int* __restrict__ cnt_p, int cap_p,
        uint32_t* __restrict__ list_c, int* __restrict__ cnt_c, int cap_c,
        int* __restrict__ status)
 {
     __shared__ double4 s_img[IMG ? IMG_LDS : 1];
+    __shared__ RowSpan s_rows[TABLE ? ROW_LDS : 1];
     load_images<IMG>(s_img, img_tab, g.n_img);
+    if constexpr (TABLE)
+        for (int i = threadIdx.x; i < g.nrows && i < ROW_LDS; i += BLOCK) s_rows[i] = row_tab[i];
     __syncthreads();
     const double rp2w = rp2 * (1.0 + 1e-12), rc2w = rc2 * (1.0 + 1e-12);
     const int lane = threadIdx.x & (WAVE - 1);
     const int nb0 = g.nb[0], nb1 = g.nb[1], nb2 = g.nb[2];
     const int n1 = 2 * g.timg[1] + 1, n2 = 2 * g.timg[2] + 1;
     const int n1r = 2 * g.reach[1] + 1, n2r = 2 * g.reach[2] + 1;
-    const int nrows = n1r * n2r;
+    const int nrows = TABLE ? g.nrows : n1r * n2r;
     const uint32_t img_self = (uint32_t)((g.timg[0] * n1 + g.timg[1]) * n2 + g.timg[2]);
     // the waves of XCD x take the bins of slab x round-robin
     const int per = gridDim.x >> 3;
@@ -331,6 +338,7 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
         }
         const int spr = ta1 - ta0 + 1;  // segments per stencil row
         const int nseg = nrows * spr;
+        const int ncnseg = g.ncnrows * spr;  // TABLE: segments of the rows within R_cn reach
         for (int a0 = s; a0 < e; a0 += WAVE) {
             const int na = (e - a0) < WAVE ? (e - a0) : WAVE;
             int np = 0, nc = 0;  // lane t counts the entries of atom a0 + t
@@ -340,8 +348,22 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
                 const int sg = sb + lane;
                 if (sg < nseg) {
                     const int r = sg / spr, q = sg - r * spr;
-                    const int u1 = b1 + (r % n1r - g.reach[1]);
-                    const int u2 = b2 + (r / n1r - g.reach[2]);
+                    int u1, u2;
+                    if constexpr (TABLE) {
+                        // the row's own span of first-axis bins
+                        const RowSpan rs = r < ROW_LDS ? s_rows[r] : row_tab[r];
+                        u1 = b1 + rs.d1;
+                        u2 = b2 + rs.d2;
+                        ua = b0 + rs.lo;
+                        ub = b0 + rs.hi;
+                        if (!g.pbc[0]) {
+                            ua = ua < 0 ? 0 : ua;
+                            ub = ub >= nb0 ? nb0 - 1 : ub;
+                        }
+                    } else {
+                        u1 = b1 + (r % n1r - g.reach[1]);
+                        u2 = b2 + (r / n1r - g.reach[2]);
+                    }
                     int t1 = 0, w1 = u1, t2 = 0, w2 = u2;
                     bool ok = true;
                     if (g.pbc[1]) { t1 = floordiv(u1, nb1); w1 = u1 - t1 * nb1; }
@@ -361,6 +383,14 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
                 const int incl = wave_incl_scan(len);
                 const int excl = incl - len;  // non-decreasing over the lanes
                 const int total = __builtin_amdgcn_readlane(incl, WAVE - 1);
+                // TABLE: candidates [0, cn_total) come from the rows within R_cn
+                // reach (they come first), the rest skip the R_cn test
+                int cn_total = total;
+                if constexpr (TABLE) {
+                    const int last_cn = min(ncnseg - sb, WAVE) - 1;
+                    const int at_last = __shfl(incl, last_cn < 0 ? 0 : last_cn, WAVE);
+                    cn_total = last_cn < 0 ? 0 : __builtin_amdgcn_readfirstlane(at_last);
+                }
                 for (int kb = 0; kb < total; kb += LIST_AHEAD * WAVE) {
                     // candidates kb + u*64 + lane: sorted atom, image, position; each
                     // lies in the last segment whose offset is <= its index
@@ -415,7 +445,8 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
                             const double r2 = dx * dx + dy * dy + dz * dz;
                             const bool other = valid[u] & (code[u] != self);
                             const bool inp = other & (r2 < rp2w);
-                            const bool inc = other & (r2 < rc2w);
+                            const bool inc =
+                                (!TABLE || kb + u * WAVE < cn_total) & other & (r2 < rc2w);
                             const unsigned long long bp = __ballot(inp);
                             const unsigned long long bc = __ballot(inc);
                             if constexpr (!COUNT) {
@@ -536,22 +567,34 @@ void launch_update(int n, const double* pos, const int* perm,
 }
 
 void launch_list(int n, const double4* pos_s, const int* bin_start, const int* slab, const Geo& g,
-                 const double4* img_tab, double rp2, double rc2, uint32_t* list_p,
-                 int* cnt_p, int cap_p, uint32_t* list_c, int* cnt_c, int cap_c,
-                 int count_only, int* status, hipStream_t s)
+                 const RowSpan* row_tab, const double4* img_tab, double rp2, double rc2,
+                 uint32_t* list_p, int* cnt_p, int cap_p, uint32_t* list_c, int* cnt_c,
+                 int cap_c, int count_only, int* status, hipStream_t s)
 {
     if (n <= 0) return;
-#define D3_LIST(I, C)                                                                          \
-    hipLaunchKernelGGL((k_list<I, C>), dim3(pass_blocks((const void*)&k_list<I, C>, g.nbins)), \
-                       dim3(BLOCK), 0, s, pos_s, bin_start, slab, g, img_tab, rp2, rc2, list_p,  \
+#define D3_LIST(I, C, T)                                                                       \
+    hipLaunchKernelGGL((k_list<I, C, T>),                                                      \
+                       dim3(pass_blocks((const void*)&k_list<I, C, T>, g.nbins)), dim3(BLOCK), \
+                       0, s, pos_s, bin_start, slab, g, row_tab, img_tab, rp2, rc2, list_p,    \
                        cnt_p, cap_p, list_c, cnt_c, cap_c, status)
     const bool lds = g.n_img <= IMG_LDS;
-    if (count_only) {
-        if (lds) D3_LIST(true, true);
-        else D3_LIST(false, true);
+    // the row table (trimmed, R_cn rows first) only for deep stencils
+    if (g.nrows > 0) {
+        if (count_only) {
+            if (lds) D3_LIST(true, true, true);
+            else D3_LIST(false, true, true);
+        } else {
+            if (lds) D3_LIST(true, false, true);
+            else D3_LIST(false, false, true);
+        }
     } else {
-        if (lds) D3_LIST(true, false);
-        else D3_LIST(false, false);
+        if (count_only) {
+            if (lds) D3_LIST(true, true, false);
+            else D3_LIST(false, true, false);
+        } else {
+            if (lds) D3_LIST(true, false, false);
+            else D3_LIST(false, false, false);
+        }
     }
 #undef D3_LIST
 }

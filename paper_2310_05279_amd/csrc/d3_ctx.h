@@ -61,7 +61,7 @@ struct d3_ctx {
     bool counts_clean = false;  // bin counts and scatter cursors are zero
     // cell-sorted data
     d3::Buf bin_of, shift, count, bin_start, scan_tmp, perm_tmp, perm, slab;
-    d3::Buf pos_s, shift_s, ref_s, type_copy, img_tab;
+    d3::Buf pos_s, shift_s, ref_s, type_copy, img_tab, row_tab;
     // lists
     d3::Buf list_p, cnt_p, list_c, cnt_c;
     int cap_p = 0, cap_c = 0;
@@ -87,7 +87,7 @@ struct d3_ctx {
     {
         return {&d_tab, &d_c6, &d_pc, &bin_of, &shift, &count, &bin_start,
                 &scan_tmp, &perm_tmp, &perm, &slab, &pos_s, &shift_s, &ref_s, &type_copy,
-                &img_tab, &list_p, &cnt_p, &list_c, &cnt_c, &cn, &cnf, &w, &wd, &P,
+                &img_tab, &row_tab, &list_p, &cnt_p, &list_c, &cnt_c, &cn, &cnf, &w, &wd, &P,
                 &Pf, &G, &Fp, &U, &Vp, &vpart, &vpart2, &status, &maxcnt, &ticket, &md_scratch};
     }
 };

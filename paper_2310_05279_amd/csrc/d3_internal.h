@@ -31,7 +31,18 @@ struct Geo {
     int img_bits;    // list entry = (j << img_bits) | image
     int n_img;
     int nbins;
+    int nrows;       // rows of the stencil row table (0: no table, every row)
+    int ncnrows;     // the first ncnrows rows can hold pairs within the R_cn list cutoff
 };
+
+// One stencil row of the list build with a row table: bins (b0 + lo ..
+// b0 + hi, b1 + d1, b2 + d2) of the home bin (b0, b1, b2), the bins of the
+// row whose nearest points lie within the list cutoff.
+struct RowSpan {
+    int d1, d2, lo, hi;
+};
+constexpr long MAX_ROW_TAB = 4096;  // largest stencil (rows) given a row table
+constexpr int ROW_TABLE_REACH = 4;  // a row table from this stencil reach on
 
 // Per-element data used inside kernels (kept in global memory).
 struct ElemTab {
@@ -59,6 +70,7 @@ void launch_rank(int n, const int* perm_tmp, const int* bin_of, const int* bin_s
                  int* perm, double4* pos_s, double4* shift_s, double4* ref_s, int nbins,
                  int* slab, int* count, hipStream_t s);
 void launch_list(int n, const double4* pos_s, const int* bin_start, const int* slab, const Geo& g,
+                 const RowSpan* row_tab,
                  const double4* img_tab, double rp2, double rc2, uint32_t* list_p,
                  int* cnt_p, int cap_p, uint32_t* list_c, int* cnt_c, int cap_c,
                  int count_only, int* status, hipStream_t s);

@@ -171,6 +171,38 @@ def test_dense_block_in_vacuum_large_bins():
     compare(gpu, ref, 1500, label="block")
 
 
+@pytest.mark.parametrize("mode", ["plain", "prec"])
+def test_long_cutoffs_50_25(mode):
+    """R_pot = 50 A and R_cn = 25 A (the long-cutoff regime): ~21 000
+    entries per atom, a 27-bin stencil of narrow bins, images two cells out
+    of a 2 000-atom MOF-like cube."""
+    m = synth.mof_like(2000, seed=50)
+    prm = dict(r_pot=50.0, r_cn=25.0)
+    print("long cutoffs", mode, flush=True)
+    ref = R.d3(m["pos"], m["types"], m["cell"], m["pbc"], TAB, **prm)
+    gpu = run_gpu(m, mode=mode, prm=prm)
+    print("long: list stats %s" % gpu["stats"], flush=True)
+    assert gpu["stats"]["max_pot"] > 20000
+    if mode == "plain":
+        compare(gpu, ref, 2000, label="long")
+    else:
+        compare(gpu, ref, 2000, tol_e=1e-6, tol_f=1e-4, tol_w_rel=1e-5, label="long-prec")
+
+
+def test_long_cutoffs_open_axis():
+    """R_pot = 30 A and R_cn = 15 A on a 12 x 12 AB bilayer (periodic in
+    plane, open along z): a deep stencil whose row table must leave the
+    open axis unbounded (atoms outside the cell join its edge bins)."""
+    g = synth.bilayer_graphene(12, 12, seed=12)
+    g = dict(g)
+    g["pos"] = g["pos"] + np.array([0.0, 0.0, -12.0])  # the lower layer lies below the cell
+    prm = dict(r_pot=30.0, r_cn=15.0)
+    ref = R.d3(g["pos"], g["types"], g["cell"], g["pbc"], TAB, **prm)
+    gpu = run_gpu(g, prm=prm)
+    print("open-axis long: list stats %s" % gpu["stats"], flush=True)
+    compare(gpu, ref, g["pos"].shape[0], label="open-long")
+
+
 def test_mof_24000_plain_config2():
     """The 24 000-atom MOF-like cell: full comparison with the C oracle."""
     m = synth.mof_like(24000)
