@@ -206,6 +206,21 @@ int d3_status(d3_ctx *ctx);
  * double[6].  Synchronises. */
 int d3_list_stats(d3_ctx *ctx, double *out);
 
+/* The bin layout a build would use, computed on the host only (no device
+ * work; for inspection and tests).  cell: host double[9]; pbc: host
+ * int32[3]; rlist: the longer list cutoff (R_pot or R_cn, plus the skin);
+ * rcn: the R_cn list cutoff (<= rlist); n atoms.  Out: nb[3] bins and
+ * reach[3] stencil reach along each lattice vector; *nrows rows of the
+ * stencil row table (0: no table, the kernel walks the full stencil), of
+ * which the first *ncnrows can hold pairs within rcn; rows (host int32
+ * [4*max_rows] or NULL) receives (d1, d2, lo, hi) per row: bins (b0 + lo ..
+ * b0 + hi, b1 + d1, b2 + d2) of home bin (b0, b1, b2), those whose nearest
+ * points lie within rlist.  Errors: INVALID_ARG, CELL. */
+int d3_bin_plan(const double *cell, const int32_t *pbc, double rlist,
+                double rcn, int64_t n, int32_t *nb, int32_t *reach,
+                int32_t *nrows, int32_t *ncnrows, int32_t *rows,
+                int32_t max_rows);
+
 /* Per-phase timing with HIP events recorded on the caller's stream around
  * each group of launches: 0 neighbour build, 1 position update, 2 CN and
  * weights, 3 dispersion pass, 4 chain pass with the final reductions,

@@ -798,6 +798,34 @@ int d3_list_stats(d3_ctx* c, double* out)
     return D3_OK;
 }
 
+int d3_bin_plan(const double* cell, const int32_t* pbc, double rlist, double rcn, int64_t n,
+                int32_t* nb, int32_t* reach, int32_t* nrows, int32_t* ncnrows, int32_t* rows,
+                int32_t max_rows)
+{
+    if (!cell || !pbc || !nb || !reach || !nrows || !ncnrows)
+        return fail(D3_ERR_INVALID_ARG, "NULL argument");
+    if (!(rlist > 0.0) || !(rcn > 0.0) || rcn > rlist || n < 0 || max_rows < 0)
+        return fail(D3_ERR_INVALID_ARG, "bad cutoffs, atom count or row capacity");
+    Geo g{};
+    std::vector<double4> imgs;
+    std::vector<RowSpan> table;
+    D3CHK(make_geo(cell, pbc, rlist, rcn, n, g, imgs, table));
+    for (int k = 0; k < 3; k++) {
+        nb[k] = g.nb[k];
+        reach[k] = g.reach[k];
+    }
+    *nrows = g.nrows;
+    *ncnrows = g.ncnrows;
+    if (rows)
+        for (int r = 0; r < g.nrows && r < max_rows; r++) {
+            rows[4 * r] = table[r].d1;
+            rows[4 * r + 1] = table[r].d2;
+            rows[4 * r + 2] = table[r].lo;
+            rows[4 * r + 3] = table[r].hi;
+        }
+    return D3_OK;
+}
+
 }  // extern "C"
 
 namespace d3 {

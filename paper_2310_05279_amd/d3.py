@@ -85,6 +85,7 @@ _SIGS = {
     "d3_energy_forces_virial": (_c_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _c_u32, _vp]),
     "d3_evaluate": (_c_i32, [_vp, _vp, ctypes.POINTER(d3_outputs), _c_u32, _vp]),
     "d3_status": (_c_i32, [_vp]),
+    "d3_bin_plan": (_c_i32, [_vp, _vp, _c_d, _c_d, _c_i64, _vp, _vp, _vp, _vp, _vp, _c_i32]),
     "d3_list_stats": (_c_i32, [_vp, _vp]),
     "d3_set_timing": (_c_i32, [_vp, _c_i32]),
     "d3_get_timing": (_c_i32, [_vp, _vp, _vp]),
@@ -202,6 +203,22 @@ def d3_evaluate(ctx, pos, energy, forces=None, virial=None, atom_energy=None,
     out = d3_outputs(p(energy), p(forces), p(virial), p(atom_energy), p(atom_virial),
                      p(velocities), p(heat_current))
     _check(lib().d3_evaluate(ctx, _ptr(pos), ctypes.byref(out), int(flags), _stream(stream)))
+
+
+def d3_bin_plan(cell, pbc, rlist, rcn, n, max_rows=8192):
+    """Host-side bin layout of a build: bins, stencil reach and row table."""
+    cell = np.ascontiguousarray(cell, dtype=np.float64).reshape(9)
+    pbc = np.ascontiguousarray(pbc, dtype=np.int32).reshape(3)
+    nb = np.zeros(3, np.int32)
+    reach = np.zeros(3, np.int32)
+    nrows = ctypes.c_int32()
+    ncn = ctypes.c_int32()
+    rows = np.zeros((max_rows, 4), np.int32)
+    _check(lib().d3_bin_plan(cell.ctypes.data, pbc.ctypes.data, float(rlist), float(rcn),
+                             int(n), nb.ctypes.data, reach.ctypes.data, ctypes.byref(nrows),
+                             ctypes.byref(ncn), rows.ctypes.data, int(max_rows)))
+    return {"nb": nb, "reach": reach, "rows": rows[:min(nrows.value, max_rows)],
+            "ncnrows": ncn.value}
 
 
 def d3_status(ctx):
