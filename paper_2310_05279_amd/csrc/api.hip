@@ -609,8 +609,7 @@ int d3_create(const d3_params* prm, const d3_table* tab, d3_ctx** out)
     if ((r = ensure(c->d_tab, sizeof(ElemTab))) ||
         (r = ensure(c->d_c6, c6.size() * sizeof(double))) ||
         (r = ensure(c->d_pc, pc.size() * sizeof(double4))) ||
-        (r = ensure(c->status, 256)) || (r = ensure(c->maxcnt, 256)) ||
-        (r = ensure(c->ticket, 256))) {
+        (r = ensure(c->status, 256)) || (r = ensure(c->maxcnt, 256))) {
         d3_destroy(c);
         return r;
     }
@@ -618,7 +617,6 @@ int d3_create(const d3_params* prm, const d3_table* tab, d3_ctx** out)
     hipError_t e2 = hipMemcpy(c->d_c6.p, c6.data(), c6.size() * sizeof(double), hipMemcpyHostToDevice);
     hipError_t e3 = hipMemcpy(c->d_pc.p, pc.data(), pc.size() * sizeof(double4), hipMemcpyHostToDevice);
     hipError_t e4 = hipMemset(c->status.p, 0, 256);
-    if (e4 == hipSuccess) e4 = hipMemset(c->ticket.p, 0, 256);
     hipError_t e5 = hipHostMalloc((void**)&c->h_status, 64, hipHostMallocDefault);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess ||
         e5 != hipSuccess) {

@@ -68,7 +68,7 @@ struct d3_ctx {
     // per-atom results
     d3::Buf cn, cnf, w, wd, P, Pf, G, Fp, U, Vp, vpart, vpart2;
     // status
-    d3::Buf status, maxcnt, ticket;
+    d3::Buf status, maxcnt;
     int* h_status = nullptr;
     hipStream_t last_stream = nullptr;
     d3::Surrogate* sur = nullptr;
@@ -88,7 +88,7 @@ struct d3_ctx {
         return {&d_tab, &d_c6, &d_pc, &bin_of, &shift, &count, &bin_start,
                 &scan_tmp, &perm_tmp, &perm, &slab, &pos_s, &shift_s, &ref_s, &type_copy,
                 &img_tab, &row_tab, &list_p, &cnt_p, &list_c, &cnt_c, &cn, &cnf, &w, &wd, &P,
-                &Pf, &G, &Fp, &U, &Vp, &vpart, &vpart2, &status, &maxcnt, &ticket, &md_scratch};
+                &Pf, &G, &Fp, &U, &Vp, &vpart, &vpart2, &status, &maxcnt, &md_scratch};
     }
 };
 
