@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 PAIR_TRAFFIC = {"fetch_kib": 24108.014, "write_kib": 1019.526,
                 "fetch_scale": 1.9999, "write_scale": 1.0,
                 "sources": ("disp.hip", "d3_device.h", "d3_internal.h"),
-                "sha256": "84bfe862e1c3520267702c18229d933b"}
+                "sha256": "c01f031f2568440766e437fa10c05714"}
 
 
 def _sources_hash(names):

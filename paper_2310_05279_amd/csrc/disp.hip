@@ -14,7 +14,9 @@
 // every element f, so a neighbour costs one 48-byte weight gather and
 // C6 = u_{Zj} . w_j, dC6/dn_i = u'_{Zj} . w_j.  The pair constants (Rd^6,
 // Rd^8, s8 R0^2) of every element pair sit in LDS too.  List codes are
-// fetched two chunks and neighbour data one chunk ahead of the arithmetic;
+// fetched two chunks ahead of the arithmetic and neighbour data is handed
+// on one chunk ahead (the compiler turns that hand-on into a load at the top
+// of the next step, which measured faster than any way of keeping it);
 // every lane loads a valid address (entries past the count read atom 0 and
 // are masked), so the loads carry no branches.
 //
@@ -146,7 +148,7 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
         double av[6] = {0, 0, 0, 0, 0, 0};  // this atom's virial (AV only)
         for (int k0 = 0; k0 < cnt; k0 += WAVE) {
             const int k = k0 + lane;
-            // prefetch: codes two chunks ahead, neighbour data one chunk ahead
+            // codes two chunks ahead; neighbour data handed on to the next step
             const uint32_t code_nn = list_code(lp, k + 2 * WAVE, cnt, cap_p);
             Nbr<F32> nb_n;
             fetch<F32>(nb_n, code_n, img_bits, pos_s, W, Wf);
