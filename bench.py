@@ -214,7 +214,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the D3 path here is single-GPU "
-              "(see DESIGN.md for how it would shard); run with --gpus 1",
+              "(it is not sharded across GPUs); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
@@ -317,16 +317,28 @@ def main():
         print("[bench] surrogate %s" % json.dumps(extra["surrogate"]), file=sys.stderr, flush=True)
 
         def forms(big, steps, modes):
-            entry = {}
+            """Speed of each form on a large cell, and the deviation of the
+            precision and surrogate forms from the plain FP64 result."""
+            entry, ref = {}, None
+            nbig = big["pos"].shape[0]
             for mode in modes:
                 run = Runner(big, table, mode)
                 if mode == "surrogate":
                     d3mod.d3_c6_surrogate_set_weights(run.calc.ctx, weights)
                 msb = run.timed(steps, 2)
                 phb = run.phases(5)
+                got = (run.out["forces"].cpu().numpy(), float(run.out["energy"].item()),
+                       run.out["virial"].cpu().numpy())
                 run.close()
-                entry[mode] = {"atom_steps_per_s": big["pos"].shape[0] / (msb * 1e-3),
+                entry[mode] = {"atom_steps_per_s": nbig / (msb * 1e-3),
                                "ms_per_step": msb, "phase_ms": phb}
+                if mode == "plain":
+                    ref = got
+                elif ref is not None:
+                    entry[mode].update({
+                        "max_abs_dF_vs_plain": float(np.abs(got[0] - ref[0]).max()),
+                        "abs_dE_per_atom_vs_plain": abs(got[1] - ref[1]) / nbig,
+                        "max_abs_dW_vs_plain": float(np.abs(got[2] - ref[2]).max())})
             return entry
 
         for name, big, steps, modes in (
@@ -381,6 +393,35 @@ def main():
                         "etot_drift_per_atom_eV": float((thermo[-1, 2] - thermo[0, 2]) / nb)}
         extra["md_nve_mof_1M"] = md
         print("[bench] md %s" % json.dumps(md), file=sys.stderr, flush=True)
+
+        # the paper's own throughput shape (Table I): a 40 000-atom AB bilayer
+        # (100 x 100 supercell), one step with a build, and NVE MD as above
+        bl = synth.bilayer_graphene(100, 100, seed=40000)
+        nbl = bl["pos"].shape[0]
+        vb, mb = synth.maxwell_velocities(bl["types"], 300.0, seed=301)
+        entry = {"n_atoms": nbl}
+        for mode in ("plain", "prec"):
+            run = Runner(bl, table, mode)
+            msb = run.timed(50, 5)
+            run.close()
+            run = Runner(bl, table, mode, skin=1.0)
+            pos = run.calc.pos.clone()
+            vel = torch.as_tensor(vb, device="cuda")
+            mss = torch.as_tensor(mb, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            thermo, reb = d3mod.d3_md_nve(run.calc.ctx, args.md_steps, 1.0, pos, vel, mss,
+                                          every=args.md_steps)
+            dt = time.perf_counter() - t0
+            run.close()
+            entry[mode] = {"atom_steps_per_s_build_every_step": nbl / (msb * 1e-3),
+                           "ms_per_step_build_every_step": msb,
+                           "md_atom_steps_per_s": nbl * args.md_steps / dt,
+                           "md_ms_per_step": 1e3 * dt / args.md_steps, "md_rebuilds": reb,
+                           "md_etot_drift_per_atom_eV":
+                               float((thermo[-1, 2] - thermo[0, 2]) / nbl)}
+        extra["bilayer_40k"] = entry
+        print("[bench] bilayer 40k %s" % json.dumps(entry), file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:

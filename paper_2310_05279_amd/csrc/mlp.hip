@@ -2,7 +2,8 @@
 // the two coordination numbers to (C6, dC6/dn_i, dC6/dn_j) of Eq. 3.  It is
 // not part of the paper; it approximates Eq. 3, is trained on samples that
 // the exact interpolation labels, and exact Eq. 3 stays both the fallback
-// (coordination numbers outside the trained box) and the judge of its error.
+// (coordination numbers outside the trained box) and the reference its
+// error is measured against.
 //
 // Network, per unordered element pair (e <= f), row-vector convention,
 // inputs x = 2 n / cn_hi - 1:

@@ -109,7 +109,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise OSError("libd3.so not built at %s (run __graft_entry__.build())" % LIB_PATH)
+            raise OSError("libd3.so not built at %s (run paper_2310_05279_amd/build.py)"
+                          % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
