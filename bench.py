@@ -329,9 +329,20 @@ def main():
                 phb = run.phases(5)
                 got = (run.out["forces"].cpu().numpy(), float(run.out["energy"].item()),
                        run.out["virial"].cpu().numpy())
+                st = run.calc.stats()
                 run.close()
                 entry[mode] = {"atom_steps_per_s": nbig / (msb * 1e-3),
                                "ms_per_step": msb, "phase_ms": phb}
+                if mode in ("plain", "prec"):
+                    # the dispersion pass against its ALU roof: unique pairs from
+                    # the list length (the lists hold exactly the pairs within
+                    # R_pot), flops per pair at the mean reference count
+                    kbar = float(np.asarray(table["n_ref"])[big["types"]].mean())
+                    fl = 0.5 * st["mean_pot"] * nbig * _flops_per_pair(kbar, kbar)
+                    peak = FP64_VECTOR_PEAK_TFLOPS if mode == "plain" else FP32_VECTOR_PEAK_TFLOPS
+                    ach = fl / (phb["pair"] * 1e-3) / 1e12
+                    entry[mode]["pair_roofline"] = {"achieved_TFLOPs": ach, "peak_TFLOPs": peak,
+                                                    "frac": ach / peak}
                 if mode == "plain":
                     ref = got
                 elif ref is not None:

@@ -106,6 +106,44 @@ def test_mixed_open_and_periodic_axes_and_unwrapped_positions():
     compare(gpu, ref, 600, label="slab")
 
 
+def _random_cell_case(seed):
+    """A small random cell: skewed lattice vectors of 4-16 A, any mix of
+    periodic and open axes, 3-40 atoms of random elements (some outside the
+    cell), cutoffs from 5 to 30 A with R_cn from R_pot/4 to R_pot."""
+    rng = np.random.default_rng(1000 + seed)
+    while True:
+        cell = np.diag(rng.uniform(4.0, 16.0, 3)) + rng.uniform(-3.0, 3.0, (3, 3)) * \
+            (1 - np.eye(3))
+        if abs(np.linalg.det(cell)) > 0.2 * np.prod(np.linalg.norm(cell, axis=1)):
+            break
+    pbc = rng.integers(0, 2, 3).astype(np.int32)
+    n = int(rng.integers(3, 41))
+    for _ in range(1000):
+        pos = rng.uniform(-0.3, 1.3, (n, 3)) @ cell
+        if n < 2 or O.entries(pos, cell, pbc, 0.9)[0].size == 0:
+            break
+    types = rng.integers(0, 5, n).astype(np.int32)
+    r_pot = float(rng.uniform(5.0, 30.0))
+    r_cn = float(rng.uniform(0.25, 1.0)) * r_pot
+    return {"pos": pos, "types": types, "cell": cell, "pbc": pbc}, dict(r_pot=r_pot, r_cn=r_cn)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_small_cells(seed):
+    """Random small cells against the NumPy oracle in the plain and the
+    precision forms: shallow and deep stencils, with and without row tables,
+    open axes with atoms beyond their faces, many images."""
+    s, prm = _random_cell_case(seed)
+    n = s["pos"].shape[0]
+    print("random cell %d: n=%d pbc=%s r_pot=%.2f r_cn=%.2f" % (seed, n, s["pbc"], prm["r_pot"],
+                                                             prm["r_cn"]), flush=True)
+    ref = O.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB, O.Params(**prm))
+    gpu = run_gpu(s, prm=prm)
+    compare(gpu, ref, n, label="random-%d" % seed)
+    gpu = run_gpu(s, mode="prec", prm=prm)
+    compare(gpu, ref, n, tol_e=1e-6, tol_f=1e-4, tol_w_rel=1e-5, label="random-prec-%d" % seed)
+
+
 def test_finite_cluster_no_pbc():
     c = synth.cluster(80, 7.0, seed=5)
     cell = np.eye(3) * 14.0
