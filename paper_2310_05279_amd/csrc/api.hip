@@ -382,9 +382,11 @@ int alloc_atoms(d3_ctx* c, int64_t n)
 int alloc_proj(d3_ctx* c, int mode)
 {
     const size_t N = (size_t)(c->n > 0 ? c->n : 1);
-    // per-atom weight rows: 6 doubles (plain) or 8 floats (precision form)
-    if (mode == D3_MODE_PREC_F32) return ensure(c->Pf, N * 8 * sizeof(float));
-    return ensure(c->P, N * 6 * sizeof(double));
+    // per-atom neighbour data of the dispersion pass, 16-byte pieces in
+    // whole blocks of PBLK atoms
+    if (mode == D3_MODE_PREC_F32)
+        return ensure(c->Pf, (N + PBLKF - 1) / PBLKF * PBLKF * NPIECEF * 4 * sizeof(float));
+    return ensure(c->P, (N + PBLK - 1) / PBLK * PBLK * NPIECE * 4 * sizeof(double));
 }
 
 // Binning, counting sort and list construction on stream s.

@@ -89,10 +89,23 @@ k_cn(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_t
                 w[(size_t)i * MAXREF + rl] = wl;
                 wd[(size_t)i * MAXREF + rl] = wdl;
             }
+            // the atom's pieces for the dispersion pass: lanes 0..4 the
+            // weights, lanes 5..7 the position, lane 8 (FP32) the species
+            const double pv = rl == 5 ? pi.x : (rl == 6 ? pi.y : pi.z);
             if (F32) {
-                if (rl < WROWF) Wf[(size_t)i * WROWF + rl] = (float)wl;
-            } else if (rl < WROW) {
-                W[(size_t)i * WROW + rl] = wl;
+                float* p0 = Wf + piece_at(NPIECEF, PBLKF, 0, i) * 4;  // x, y
+                float* p1 = Wf + piece_at(NPIECEF, PBLKF, 1, i) * 4;  // z, w0, w1
+                float* p2 = Wf + piece_at(NPIECEF, PBLKF, 2, i) * 4;  // w2, w3, w4, species
+                if (rl < 2) p1[2 + rl] = (float)wl;
+                else if (rl < MAXREF) p2[rl - 2] = (float)wl;
+                else if (rl < 7) ((double*)p0)[rl - 5] = pv;
+                else if (rl == 7) *(double*)p1 = pv;
+                else if (rl == 8) ((int*)p2)[3] = zi;
+            } else {
+                // slot s (x, y, z, w0..w4) is double s % 4 of piece s / 4
+                const int s = rl < MAXREF ? 3 + rl : rl - 5;
+                const double v = rl < MAXREF ? (((zi >> rl) & 1) && rl < 4 ? -wl : wl) : pv;
+                if (rl < 8) W[piece_at(NPIECE, PBLK, s >> 2, i) * 4 + (s & 3)] = v;
             }
         }
     }

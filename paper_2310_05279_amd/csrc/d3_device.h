@@ -105,8 +105,6 @@ __device__ __forceinline__ float wave_sum(float v)
 namespace d3 {
 
 constexpr int IMG_LDS = 128;   // image translations cached in LDS
-constexpr int WROW = 6;        // doubles per FP64 weight row (5 + pad)
-constexpr int WROWF = 8;       // floats per FP32 weight row (5 + pad)
 
 __device__ __forceinline__ int zbits(double w) { return __double2loint(w); }
 

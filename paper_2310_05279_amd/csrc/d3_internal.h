@@ -13,6 +13,28 @@ constexpr int MAXREF = D3_MAX_REF;
 constexpr int MAXELEM = D3_MAX_ELEM;
 constexpr int BLOCK = 256;          // 4 waves per workgroup
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
+// Per-atom neighbour data of the dispersion pass (position and Gaussian
+// weights), in pieces stored in blocks of a few atoms, piece-major inside a
+// block (piece q of atom j at piece_at(np, blk, q, j)): the lanes of a wave
+// that read one piece of neighbours lying close together in the sorted
+// order share cache lines, and all the pieces of an atom lie in one block.
+//  FP64 form, 2 pieces of 32 bytes, 4 atoms per block: (x, y, z, w0),
+//    (w1, w2, w3, w4); the species is carried by the sign bits of w0..w3
+//    (bit k of the species in the sign of w_k): every weight is >= 0, so
+//    the reader takes |w| and loses nothing;
+//  FP32 form, 3 pieces of 16 bytes, 8 atoms per block: (x, y), (z, (w0,
+//    w1)), (w2, w3, w4, species), the position in FP64, the weights in FP32
+//    and the species as an int.
+constexpr int NPIECE = 2;   // FP64 form: 32-byte pieces
+constexpr int PBLK = 4;     // FP64 form: atoms per block
+constexpr int NPIECEF = 3;  // FP32 form: 16-byte pieces
+constexpr int PBLKF = 8;    // FP32 form: atoms per block
+// index, in pieces, of piece q of atom j (np pieces per atom, blk atoms per block)
+__host__ __device__ inline size_t piece_at(int np, int blk, int q, size_t j)
+{
+    return ((j / blk) * np + q) * blk + (j % blk);
+}
+static_assert(MAXELEM <= 16, "four sign bits carry the species in the FP64 form");
 
 // device status bits (OR-ed by kernels, read by d3_status)
 constexpr int ST_SPECIES = 1;

@@ -11,8 +11,9 @@
 // atoms and so is its normaliser, hence C6_ij = w_i^T M_{Zi Zj} w_j with
 // w the normalised per-atom weights.  When a wave takes atom i it forms in
 // LDS the row vectors u_f = w_i^T M_{Zi f} and u'_f = w_i'^T M_{Zi f} for
-// every element f, so a neighbour costs one 48-byte weight gather and
-// C6 = u_{Zj} . w_j, dC6/dn_i = u'_{Zj} . w_j.  The pair constants (Rd^6,
+// every element f, so a neighbour costs one gather of its position,
+// species and weights (64 bytes, laid out in blocks written by the CN pass)
+// and C6 = u_{Zj} . w_j, dC6/dn_i = u'_{Zj} . w_j.  The pair constants (Rd^6,
 // Rd^8, s8 R0^2) of every element pair sit in LDS too.  List codes are
 // fetched two chunks ahead of the arithmetic and neighbour data is handed
 // on one chunk ahead (the compiler turns that hand-on into a load at the top
@@ -44,37 +45,44 @@ __device__ __forceinline__ double recip(double x)
     return fma(y, e, y);
 }
 
+// One neighbour's position, weights and species (see piece_at).
 template <bool F32>
 struct Nbr;
 template <>
 struct Nbr<false> {
-    double4 p;
-    double2 w01, w23;
-    double w4;
+    double4 a;  // x, y, z, w0
+    double4 b;  // w1..w4
 };
 template <>
 struct Nbr<true> {
-    double4 p;
-    float4 w03;
-    float w4;
+    double2 xy;
+    double2 zw;  // z, (w0, w1)
+    float4 b;    // w2, w3, w4, species
 };
 
 template <bool F32>
 __device__ __forceinline__ void fetch(Nbr<F32>& nb, uint32_t code, int img_bits,
-                                      const double4* __restrict__ pos_s,
                                       const double* __restrict__ W, const float* __restrict__ Wf)
 {
     const uint32_t j = code >> img_bits;
-    nb.p = pos_s[j];
     if constexpr (F32) {
-        nb.w03 = *(const float4*)(Wf + (size_t)j * WROWF);
-        nb.w4 = Wf[(size_t)j * WROWF + 4];
+        const float4* r = (const float4*)Wf + piece_at(NPIECEF, PBLKF, 0, j);
+        nb.xy = __builtin_bit_cast(double2, r[0]);
+        nb.zw = __builtin_bit_cast(double2, r[PBLKF]);
+        nb.b = r[2 * PBLKF];
     } else {
-        const double2* r = (const double2*)(W + (size_t)j * WROW);
-        nb.w01 = r[0];
-        nb.w23 = r[1];
-        nb.w4 = W[(size_t)j * WROW + 4];
+        const double4* r = (const double4*)W + piece_at(NPIECE, PBLK, 0, j);
+        nb.a = r[0];
+        nb.b = r[PBLK];
     }
+}
+
+// species of an FP64-form neighbour: bit k in the sign of w_k
+__device__ __forceinline__ int rec_species(const Nbr<false>& nb)
+{
+    const uint32_t h0 = (uint32_t)__double2hiint(nb.a.w), h1 = (uint32_t)__double2hiint(nb.b.x);
+    const uint32_t h2 = (uint32_t)__double2hiint(nb.b.y), h3 = (uint32_t)__double2hiint(nb.b.z);
+    return (int)((h0 >> 31) | ((h1 >> 31) << 1) | ((h2 >> 31) << 2) | ((h3 >> 31) << 3));
 }
 
 // AV: also the direct part of each atom's virial (Eq. 7), the six
@@ -143,7 +151,7 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         Nbr<F32> nb_c;
-        fetch<F32>(nb_c, code_c, img_bits, pos_s, W, Wf);
+        fetch<F32>(nb_c, code_c, img_bits, W, Wf);
         double fx = 0.0, fy = 0.0, fz = 0.0, ue = 0.0, g = 0.0;
         double av[6] = {0, 0, 0, 0, 0, 0};  // this atom's virial (AV only)
         for (int k0 = 0; k0 < cnt; k0 += WAVE) {
@@ -151,20 +159,32 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
             // codes two chunks ahead; neighbour data handed on to the next step
             const uint32_t code_nn = list_code(lp, k + 2 * WAVE, cnt, cap_p);
             Nbr<F32> nb_n;
-            fetch<F32>(nb_n, code_n, img_bits, pos_s, W, Wf);
+            fetch<F32>(nb_n, code_n, img_bits, W, Wf);
             const double4 T = image<IMG>(s_img, img_tab, code_c & img_mask);
-            const double dx = nb_c.p.x + T.x - pi.x;
-            const double dy = nb_c.p.y + T.y - pi.y;
-            const double dz = nb_c.p.z + T.z - pi.z;
+            double px, py, pz;
+            if constexpr (F32) {
+                px = nb_c.xy.x;
+                py = nb_c.xy.y;
+                pz = nb_c.zw.x;
+            } else {
+                px = nb_c.a.x;
+                py = nb_c.a.y;
+                pz = nb_c.a.z;
+            }
+            const double dx = px + T.x - pi.x;
+            const double dy = py + T.y - pi.y;
+            const double dz = pz + T.z - pi.z;
             const double r2 = dx * dx + dy * dy + dz * dz;
             const bool in = k < cnt && r2 < sc.rp2;
-            const int zj = zbits(nb_c.p.w);
+            int zj;
+            if constexpr (F32) zj = __float_as_int(nb_c.b.w);
+            else zj = rec_species(nb_c);
             const real* uz = u + zj * MAXREF;
             const real* udz = ud + zj * MAXREF;
             const double4 c = s_pc[zi * MAXELEM + zj];  // Rd^6, Rd^8, R0^2, s8 R0^2
             if constexpr (!F32) {
-                const double wj[MAXREF] = {nb_c.w01.x, nb_c.w01.y, nb_c.w23.x, nb_c.w23.y,
-                                           nb_c.w4};
+                const double wj[MAXREF] = {fabs(nb_c.a.w), fabs(nb_c.b.x), fabs(nb_c.b.y),
+                                           fabs(nb_c.b.z), nb_c.b.w};
                 double c6 = 0.0, dc6 = 0.0;
 #pragma unroll
                 for (int b = 0; b < MAXREF; b++) {
@@ -188,7 +208,8 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
                 virial_add(vir, -0.5 * dphi_r, dx, dy, dz);
                 if constexpr (AV) virial_add(av, -0.5 * dphi_r, dx, dy, dz);
             } else {
-                const float wj[MAXREF] = {nb_c.w03.x, nb_c.w03.y, nb_c.w03.z, nb_c.w03.w, nb_c.w4};
+                const float2 w01 = __builtin_bit_cast(float2, nb_c.zw.y);
+                const float wj[MAXREF] = {w01.x, w01.y, nb_c.b.x, nb_c.b.y, nb_c.b.z};
                 float c6 = 0.0f, dc6 = 0.0f;
 #pragma unroll
                 for (int b = 0; b < MAXREF; b++) {

@@ -370,6 +370,28 @@ def test_empty_and_single_atom():
     calc.close()
 
 
+def test_list_encoding_limit():
+    """A list entry packs (atom, image) into 32 bits: a system whose atom
+    count and periodic images do not fit is refused on the host before any
+    device work, and the context stays usable."""
+    _torch()
+    from paper_2310_05279_amd import d3
+    calc = d3.D3(TAB, r_pot=60.0, r_cn=6.0)
+    # 60 A over a 10 A cube: 2 bins and 13 images per axis, 2197 images, 12 bits
+    n = (1 << (32 - 12)) + 1
+    pos = np.random.default_rng(0).uniform(0.0, 10.0, (n, 3))
+    with pytest.raises(d3.D3Error) as ei:
+        calc.build(pos, np.zeros(n, np.int32), np.eye(3) * 10.0, (1, 1, 1))
+    assert ei.value.code == d3.D3_ERR_CELL
+    assert "32-bit" in str(ei.value)
+    s = synth.bilayer_graphene()
+    calc.build(s["pos"], s["types"], s["cell"], s["pbc"])
+    out = calc.compute()
+    ref = R.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB, r_pot=60.0, r_cn=6.0)
+    assert abs(float(out["energy"].cpu()[0]) - ref["energy"]) <= 1e-6 * s["pos"].shape[0]
+    calc.close()
+
+
 def test_state_errors():
     _torch()
     from paper_2310_05279_amd import d3
