@@ -39,10 +39,10 @@ HBM_PEAK_GBS = 8000.0
 # dispatch), each scaled by what the same counter read for a 512 MiB device
 # copy (FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  The figure belongs to the
 # kernel sources it was taken with: when their hash differs it is not used.
-PAIR_TRAFFIC = {"fetch_kib": 24107.985, "write_kib": 1019.394,
+PAIR_TRAFFIC = {"fetch_kib": 24113.404, "write_kib": 1019.159,
                 "fetch_scale": 1.9999, "write_scale": 1.0,
                 "sources": ("disp.hip", "d3_device.h", "d3_internal.h"),
-                "sha256": "1f1967a771e0e5e05b23ae7b27b8a09d"}
+                "sha256": "6158d49da765c79d829e52b29433002a"}
 
 
 def _sources_hash(names):
@@ -315,6 +315,21 @@ def main():
                               "abs_dE_per_atom_vs_plain": abs(esu - res_e) / n,
                               "speed_vs_plain": ms / ms_s}
         print("[bench] surrogate %s" % json.dumps(extra["surrogate"]), file=sys.stderr, flush=True)
+        # Eq. 3 as printed (K_i K_j weights per pair): the method without the
+        # factorisation, against which the surrogate also competes
+        run = Runner(system, table, "literal")
+        ms_l = run.timed(max(10, args.steps // 4), 3)
+        phl = run.phases(10)
+        fl = run.out["forces"].cpu().numpy()
+        el = float(run.out["energy"].item())
+        run.close()
+        extra["literal_eq3"] = {"atom_steps_per_s": n / (ms_l * 1e-3), "ms_per_step": ms_l,
+                                "phase_ms": phl, "pair_time_vs_plain": phl["pair"] / ph["pair"],
+                                "max_abs_dF_vs_plain": float(np.abs(fl - res_f).max()),
+                                "abs_dE_per_atom_vs_plain": abs(el - res_e) / n}
+        extra["surrogate"]["speed_vs_literal_eq3"] = ms_l / ms_s
+        extra["surrogate"]["pair_speed_vs_literal_eq3"] = phl["pair"] / phs["pair"]
+        print("[bench] literal %s" % json.dumps(extra["literal_eq3"]), file=sys.stderr, flush=True)
 
         def forms(big, steps, modes):
             """Speed of each form on a large cell, and the deviation of the
@@ -350,10 +365,14 @@ def main():
                         "max_abs_dF_vs_plain": float(np.abs(got[0] - ref[0]).max()),
                         "abs_dE_per_atom_vs_plain": abs(got[1] - ref[1]) / nbig,
                         "max_abs_dW_vs_plain": float(np.abs(got[2] - ref[2]).max())})
+            if "literal" in entry and "surrogate" in entry:
+                entry["surrogate"]["speed_vs_literal_eq3"] = (entry["literal"]["ms_per_step"] /
+                                                             entry["surrogate"]["ms_per_step"])
             return entry
 
         for name, big, steps, modes in (
-                ("mof_200k", synth.mof_like(200_000), 10, ("plain", "prec", "surrogate")),
+                ("mof_200k", synth.mof_like(200_000), 10,
+                 ("plain", "prec", "literal", "surrogate")),
                 ("mof_1M", synth.mof_like(1_000_000), 10, ("plain", "prec")),
                 ("graphene_500k", synth.bilayer_graphene(250, 500, seed=500000), 10,
                  ("plain", "prec"))):

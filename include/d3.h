@@ -76,9 +76,14 @@ typedef enum d3_mode {
     D3_MODE_PLAIN_F64 = 0, /* everything in FP64 */
     D3_MODE_PREC_F32 = 1,  /* pair arithmetic in FP32, FP64 cutoff tests,
                               Gaussian weights and reductions */
-    D3_MODE_SURROGATE = 2  /* C6 and its CN derivatives from the learned
+    D3_MODE_SURROGATE = 2, /* C6 and its CN derivatives from the learned
                               per-element-pair MLP, exact Eq. 3 outside
                               the trained CN range */
+    D3_MODE_LITERAL = 3    /* FP64 like D3_MODE_PLAIN_F64, but C6 from
+                              Eq. 3 as printed: K_i K_j Gaussian weights
+                              per pair instead of the factorised per-atom
+                              weights (a reference; the same result up to
+                              rounding, several times slower) */
 } d3_mode;
 
 /* Flags of d3_energy_forces_virial. */

@@ -552,7 +552,7 @@ int d3_create(const d3_params* prm, const d3_table* tab, d3_ctx** out)
     if (!std::isfinite(prm->s6) || !std::isfinite(prm->s8) || !std::isfinite(prm->a1) ||
         !std::isfinite(prm->a2))
         return fail(D3_ERR_INVALID_ARG, "non-finite damping parameter");
-    if (prm->mode < D3_MODE_PLAIN_F64 || prm->mode > D3_MODE_SURROGATE)
+    if (prm->mode < D3_MODE_PLAIN_F64 || prm->mode > D3_MODE_LITERAL)
         return fail(D3_ERR_INVALID_ARG, "unknown mode %d", prm->mode);
     const int ne = tab->n_elem;
     if (ne < 1 || ne > MAXELEM) return fail(D3_ERR_INVALID_ARG, "n_elem=%d outside 1..%d", ne, MAXELEM);
@@ -645,7 +645,7 @@ void d3_destroy(d3_ctx* c)
 int d3_set_mode(d3_ctx* c, int32_t mode)
 {
     if (!c) return fail(D3_ERR_INVALID_ARG, "ctx is NULL");
-    if (mode < D3_MODE_PLAIN_F64 || mode > D3_MODE_SURROGATE)
+    if (mode < D3_MODE_PLAIN_F64 || mode > D3_MODE_LITERAL)
         return fail(D3_ERR_INVALID_ARG, "unknown mode %d", mode);
     c->prm.mode = mode;
     return D3_OK;
@@ -889,6 +889,13 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
     int na = 0;
     if (mode == D3_MODE_SURROGATE) {
         D3CHK(surrogate_pair(c, sc, Vp, s, &na));
+    } else if (mode == D3_MODE_LITERAL) {
+        na = launch_pair_lit(n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img,
+                             g.img_bits, c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p,
+                             c->d_tab.as<ElemTab>(), c->d_c6.as<double>(), c->d_pc.as<double4>(),
+                             sc, c->cn.as<double>(), c->Fp.as<double>(), c->U.as<double>(),
+                             c->G.as<double>(), Vp, c->vpart.as<double>(), s);
+        HIPCHK(hipGetLastError());
     } else {
         na = launch_pair(mode, n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img,
                     g.img_bits, c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p,
@@ -900,7 +907,8 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
     }
     phase_mark(c, PH_PAIR, s);
     phase_mark(c, PH_CHAIN, s);
-    const int nb = launch_chain(mode == D3_MODE_PLAIN_F64 ? D3_MODE_PLAIN_F64 : D3_MODE_PREC_F32, n,
+    const bool f64 = mode == D3_MODE_PLAIN_F64 || mode == D3_MODE_LITERAL;
+    const int nb = launch_chain(f64 ? D3_MODE_PLAIN_F64 : D3_MODE_PREC_F32, n,
                  c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img, g.img_bits,
                  c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, c->d_tab.as<ElemTab>(),
                  sc.rc2, c->G.as<double>(), c->Fp.as<double>(), c->U.as<double>(),

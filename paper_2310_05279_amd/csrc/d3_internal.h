@@ -123,6 +123,10 @@ int launch_pair(int mode, int n, const double4* pos_s, const double4* img_tab, i
                  const ElemTab* tab, const double* c6ref, const double4* pc, PairScal sc,
                  const double* w, const double* wd, const double* W, const float* Wf, double* Fp,
                  double* U, double* G, double* Vp, double* part, hipStream_t s);
+int launch_pair_lit(int n, const double4* pos_s, const double4* img_tab, int n_img, int img_bits,
+                    const uint32_t* list_p, const int* cnt_p, int cap_p, const ElemTab* tab,
+                    const double* c6ref, const double4* pc, PairScal sc, const double* cn,
+                    double* Fp, double* U, double* G, double* Vp, double* part, hipStream_t s);
 int launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,
                   int img_bits, const uint32_t* list_c, const int* cnt_c, int cap_c,
                   const ElemTab* tab, double rc2, const double* G, const double* Fp,

@@ -45,6 +45,25 @@ __device__ __forceinline__ double recip(double x)
     return fma(y, e, y);
 }
 
+// Eq. 2 for one entry in FP64 at fixed C6: phi = -C6 gg with
+// gg = s6 / (r^6 + Rd^6) + s8 R0^2 / (r^8 + Rd^8) (c = Rd^6, Rd^8, R0^2,
+// s8 R0^2), and dphi_r = phi'(r) / r.
+struct BJ {
+    double gg, dphi_r;
+};
+__device__ __forceinline__ BJ bj_f64(double c6, double r2, const double4& c, double s6)
+{
+    const double r4 = r2 * r2, r6 = r4 * r2, r8 = r4 * r4;
+    const double A = r6 + c.x, B = r8 + c.y;
+    const double inv = recip(A * B);
+    const double t6 = B * inv, t8 = A * inv;
+    const double a6 = s6 * t6, a8 = c.w * t8;
+    BJ o;
+    o.gg = a6 + a8;
+    o.dphi_r = c6 * (6.0 * a6 * r4 * t6 + 8.0 * a8 * r6 * t8);
+    return o;
+}
+
 // One neighbour's position, weights and species (see piece_at).
 template <bool F32>
 struct Nbr;
@@ -193,20 +212,14 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
                 }
                 c6 = in ? c6 : 0.0;
                 dc6 = in ? dc6 : 0.0;
-                const double r4 = r2 * r2, r6 = r4 * r2, r8 = r4 * r4;
-                const double A = r6 + c.x, B = r8 + c.y;
-                const double inv = recip(A * B);
-                const double t6 = B * inv, t8 = A * inv;
-                const double a6 = sc.s6 * t6, a8 = c.w * t8;
-                const double gg = a6 + a8;  // -dphi/dC6
-                const double dphi_r = c6 * (6.0 * a6 * r4 * t6 + 8.0 * a8 * r6 * t8);
-                ue = fma(-0.5 * c6, gg, ue);
-                g = fma(-gg, dc6, g);
-                fx = fma(dphi_r, dx, fx);
-                fy = fma(dphi_r, dy, fy);
-                fz = fma(dphi_r, dz, fz);
-                virial_add(vir, -0.5 * dphi_r, dx, dy, dz);
-                if constexpr (AV) virial_add(av, -0.5 * dphi_r, dx, dy, dz);
+                const BJ q = bj_f64(c6, r2, c, sc.s6);
+                ue = fma(-0.5 * c6, q.gg, ue);
+                g = fma(-q.gg, dc6, g);
+                fx = fma(q.dphi_r, dx, fx);
+                fy = fma(q.dphi_r, dy, fy);
+                fz = fma(q.dphi_r, dz, fz);
+                virial_add(vir, -0.5 * q.dphi_r, dx, dy, dz);
+                if constexpr (AV) virial_add(av, -0.5 * q.dphi_r, dx, dy, dz);
             } else {
                 const float2 w01 = __builtin_bit_cast(float2, nb_c.zw.y);
                 const float wj[MAXREF] = {w01.x, w01.y, nb_c.b.x, nb_c.b.y, nb_c.b.z};
@@ -285,6 +298,149 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
     // energy enters once per wave (esum is wave-uniform), virial per lane
     const double vals[7] = {lane == 0 ? esum : 0.0, vir[0], vir[1], vir[2], vir[3], vir[4], vir[5]};
     block_partials(vals, part);
+}
+
+// The dispersion pass with C6 from Eq. 3 as printed (D3_MODE_LITERAL): for
+// every entry the Gaussian weight of each reference pair (a, b),
+// exp(-4 ((n_i - n_a)^2 + (n_j - n_b)^2)), K_i K_j exponentials, and the
+// weighted mean of the reference C6 values.  The exponents are shifted by
+// their largest value before exponentiation, an exact identity of the ratio
+// that keeps it finite.  dC6/dn_i = (S' - C6 Z') / Z with Z = sum of the
+// weights, S = sum of weight x C6_ref and ' the derivative in n_i.  It
+// reads the CNs, not the factorised weights, and is otherwise the FP64
+// dispersion pass (one wave per atom, sums gathered onto the atom).
+template <bool IMG, bool AV>
+__global__ void __launch_bounds__(BLOCK)
+k_pair_lit(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_tab,
+           int n_img, int img_bits, const uint32_t* __restrict__ list_p,
+           const int* __restrict__ cnt_p, int cap_p, const ElemTab* __restrict__ tab,
+           const double* __restrict__ c6ref, const double4* __restrict__ pc, PairScal sc,
+           const double* __restrict__ cn, double* __restrict__ Fp, double* __restrict__ U,
+           double* __restrict__ G, double* __restrict__ Vp, double* __restrict__ part)
+{
+    __shared__ double4 s_img[IMG ? IMG_LDS : 1];
+    __shared__ double4 s_pc[MAXELEM * MAXELEM];
+    __shared__ double s_cnref[MAXELEM * MAXREF];
+    __shared__ int s_nref[MAXELEM];
+    load_images<IMG>(s_img, img_tab, n_img);
+    for (int k = threadIdx.x; k < MAXELEM * MAXELEM; k += blockDim.x) s_pc[k] = pc[k];
+    if (threadIdx.x < MAXELEM * MAXREF) s_cnref[threadIdx.x] = tab->cn_ref[threadIdx.x];
+    if (threadIdx.x < MAXELEM) s_nref[threadIdx.x] = tab->n_ref[threadIdx.x];
+    __syncthreads();
+    const int lane = threadIdx.x & (WAVE - 1);
+    const uint32_t img_mask = (1u << img_bits) - 1u;
+    double vir[6] = {0, 0, 0, 0, 0, 0};
+    double esum = 0.0;
+    const Walk wk = atom_walk(n);
+    for (int i = wk.first; i < wk.end; i += wk.step) {
+        const double4 pi = pos_s[i];
+        const int zi = __builtin_amdgcn_readfirstlane(zbits(pi.w));
+        const int Ki = __builtin_amdgcn_readfirstlane(s_nref[zi]);
+        const double ni = cn[i];
+        const int cnt = min(cnt_p[i], cap_p);
+        const uint32_t* lp = list_p + (size_t)i * cap_p;
+        double da[MAXREF];
+#pragma unroll
+        for (int a = 0; a < MAXREF; a++) da[a] = ni - s_cnref[zi * MAXREF + a];
+        double fx = 0.0, fy = 0.0, fz = 0.0, ue = 0.0, g = 0.0;
+        double av[6] = {0, 0, 0, 0, 0, 0};
+        for (int k0 = 0; k0 < cnt; k0 += WAVE) {
+            const int k = k0 + lane;
+            const uint32_t code = list_code(lp, k, cnt, cap_p);
+            const uint32_t j = code >> img_bits;
+            const double4 pj = pos_s[j];
+            const double nj = cn[j];
+            const double4 T = image<IMG>(s_img, img_tab, code & img_mask);
+            const double dx = pj.x + T.x - pi.x;
+            const double dy = pj.y + T.y - pi.y;
+            const double dz = pj.z + T.z - pi.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const bool in = k < cnt && r2 < sc.rp2;
+            const int zj = zbits(pj.w);
+            const int Kj = s_nref[zj];
+            const double* M = c6ref + (size_t)(zi * MAXELEM + zj) * MAXREF * MAXREF;
+            double db[MAXREF];
+#pragma unroll
+            for (int b = 0; b < MAXREF; b++) db[b] = nj - s_cnref[zj * MAXREF + b];
+            // largest exponent over the reference pairs
+            double emax = -1e300;
+            for (int a = 0; a < Ki; a++)
+#pragma unroll
+                for (int b = 0; b < MAXREF; b++)
+                    if (b < Kj) emax = fmax(emax, -4.0 * (da[a] * da[a] + db[b] * db[b]));
+            double Z = 0.0, S = 0.0, Zd = 0.0, Sd = 0.0;
+            for (int a = 0; a < Ki; a++) {
+                const double ta = -8.0 * da[a];  // d(exponent)/dn_i
+#pragma unroll
+                for (int b = 0; b < MAXREF; b++) {
+                    if (b < Kj) {
+                        const double L = exp(-4.0 * (da[a] * da[a] + db[b] * db[b]) - emax);
+                        const double LC = L * M[a * MAXREF + b];
+                        Z += L;
+                        S += LC;
+                        Zd = fma(L, ta, Zd);
+                        Sd = fma(LC, ta, Sd);
+                    }
+                }
+            }
+            double c6 = S / Z;
+            double dc6 = (Sd - c6 * Zd) / Z;
+            c6 = in ? c6 : 0.0;
+            dc6 = in ? dc6 : 0.0;
+            const BJ q = bj_f64(c6, r2, s_pc[zi * MAXELEM + zj], sc.s6);
+            ue = fma(-0.5 * c6, q.gg, ue);
+            g = fma(-q.gg, dc6, g);
+            fx = fma(q.dphi_r, dx, fx);
+            fy = fma(q.dphi_r, dy, fy);
+            fz = fma(q.dphi_r, dz, fz);
+            virial_add(vir, -0.5 * q.dphi_r, dx, dy, dz);
+            if constexpr (AV) virial_add(av, -0.5 * q.dphi_r, dx, dy, dz);
+        }
+        if constexpr (AV) {
+            wave_sums(av);
+            if (lane == 0)
+#pragma unroll
+                for (int c = 0; c < 6; c++) Vp[6 * (size_t)i + c] = av[c];
+        }
+        double t5[5] = {fx, fy, fz, ue, g};
+        wave_sums(t5);
+        esum += t5[3];
+        if (lane == 0) {
+            Fp[3 * (size_t)i] = t5[0];
+            Fp[3 * (size_t)i + 1] = t5[1];
+            Fp[3 * (size_t)i + 2] = t5[2];
+            U[i] = t5[3];
+            G[i] = t5[4];
+        }
+    }
+    const double vals[7] = {lane == 0 ? esum : 0.0, vir[0], vir[1], vir[2], vir[3], vir[4], vir[5]};
+    block_partials(vals, part);
+}
+
+int launch_pair_lit(int n, const double4* pos_s, const double4* img_tab, int n_img, int img_bits,
+                    const uint32_t* list_p, const int* cnt_p, int cap_p, const ElemTab* tab,
+                    const double* c6ref, const double4* pc, PairScal sc, const double* cn,
+                    double* Fp, double* U, double* G, double* Vp, double* part, hipStream_t s)
+{
+    if (n <= 0) return 0;
+    const bool lds = n_img <= IMG_LDS;
+    int nblk = 0;
+#define D3_LIT(I, A)                                                                           \
+    {                                                                                          \
+        nblk = pass_blocks((const void*)&k_pair_lit<I, A>, n);                                 \
+        hipLaunchKernelGGL((k_pair_lit<I, A>), dim3(nblk), dim3(BLOCK), 0, s, n, pos_s,        \
+                           img_tab, n_img, img_bits, list_p, cnt_p, cap_p, tab, c6ref, pc, sc, \
+                           cn, Fp, U, G, Vp, part);                                            \
+    }
+    if (Vp) {
+        if (lds) D3_LIT(true, true)
+        else D3_LIT(false, true)
+    } else {
+        if (lds) D3_LIT(true, false)
+        else D3_LIT(false, false)
+    }
+#undef D3_LIT
+    return nblk;
 }
 
 int launch_pair(int mode, int n, const double4* pos_s, const double4* img_tab, int n_img,

@@ -29,7 +29,8 @@ D3_ERR_SPECIES = -8
 D3_MODE_PLAIN_F64 = 0
 D3_MODE_PREC_F32 = 1
 D3_MODE_SURROGATE = 2
-MODES = {"plain": 0, "prec": 1, "surrogate": 2}
+D3_MODE_LITERAL = 3
+MODES = {"plain": 0, "prec": 1, "surrogate": 2, "literal": 3}
 
 D3_ACCUMULATE = 1
 D3_AUTO_REBUILD = 2

@@ -272,6 +272,53 @@ def test_precision_form(case):
                          label="prec-" + case)
 
 
+def _tiny_cell():
+    cell = np.array([[5.0, 0.0, 0.0], [2.0, 4.6, 0.0], [0.5, 0.7, 5.3]])
+    s = np.random.default_rng(2).uniform(0, 1, (4, 3))
+    return {"pos": s @ cell, "types": np.array([0, 1, 2, 4], np.int32), "cell": cell,
+            "pbc": np.array([1, 1, 1], np.int32)}
+
+
+@pytest.mark.parametrize("case", ["graphene", "mof", "tiny", "twelve_elements"])
+def test_literal_eq3_mode(case):
+    """C6 from Eq. 3 as printed (K_i K_j Gaussian weights per pair, mode
+    "literal") meets the plain FP64 gates against the oracle, and agrees
+    with the factorised default to rounding: energy, forces, virial and
+    the per-atom virial."""
+    import torch
+    table = TAB
+    if case == "graphene":
+        s, oracle = synth.bilayer_graphene(), O
+    elif case == "mof":
+        s, oracle = synth.mof_like(3000, seed=31), R
+    elif case == "tiny":
+        s, oracle = _tiny_cell(), O
+    else:
+        table = synth.make_table(seed=77, n_elem=12)
+        m = synth.mof_like(900, seed=13)
+        types = np.random.default_rng(12).integers(0, 12, 900).astype(np.int32)
+        s = {"pos": m["pos"], "types": types, "cell": m["cell"], "pbc": m["pbc"]}
+        oracle = R
+    n = s["pos"].shape[0]
+    print("literal case", case, n, flush=True)
+    ref = oracle.d3(s["pos"], s["types"], s["cell"], s["pbc"], table)
+    lit, calc = run_gpu(s, mode="literal", table=table, calc_out=True)
+    compare(lit, ref, n, label="literal " + case)
+    assert np.abs(lit["cn"] - ref["cn"]).max() < 1e-12
+    fac = run_gpu(s, mode="plain", table=table)
+    scale_f = max(np.abs(fac["forces"]).max(), 1e-30)
+    assert abs(lit["energy"] - fac["energy"]) <= 1e-12 * abs(fac["energy"])
+    assert np.abs(lit["forces"] - fac["forces"]).max() <= 1e-11 * scale_f
+    assert np.abs(lit["virial"] - fac["virial"]).max() <= 1e-11 * np.abs(fac["virial"]).max()
+    vel = torch.as_tensor(np.random.default_rng(5).normal(scale=0.01, size=(n, 3)), device="cuda")
+    out = calc.compute(atom_virial=True, velocities=vel)
+    torch.cuda.synchronize()
+    W = out["atom_virial"].cpu().numpy()
+    assert np.abs(W - ref["atom_virial"]).max() <= 1e-9 * np.abs(ref["atom_virial"]).max()
+    assert np.abs(W.sum(0) - lit["virial"]).max() <= 1e-11 * np.abs(lit["virial"]).max()
+    calc.close()
+
+
 def test_deterministic_and_accumulate():
     torch = _torch()
     from paper_2310_05279_amd import d3
