@@ -186,6 +186,18 @@ class Runner:
         self.calc.close()
 
 
+def cpu_model():
+    """The host CPU's model name from /proc/cpuinfo (None if unreadable)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(system, table):
     """The C FP64 oracle (brute force over all pairs and images) timed on
     the host cores for one full E+F+W evaluation of the same cell."""
@@ -458,7 +470,8 @@ def main():
         ref, dt, threads = cpu_baseline(system, table)
         cpu = {"value": n / dt, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
                "sample": "one full FP64 E+F+W evaluation of the 24,000-atom MOF-like cell "
-                         "by the C oracle (brute force over all pairs and images), %.1f s" % dt}
+                         "by the C oracle (brute force over all pairs and images), %.1f s" % dt,
+               "cpu_model": cpu_model()}
         extra["plain_vs_oracle"] = {
             "abs_dE_per_atom": abs(res_e - ref["energy"]) / n,
             "max_abs_dF": float(np.abs(res_f - ref["forces"]).max()),
