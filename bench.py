@@ -90,8 +90,6 @@ class Runner:
         self.dev = torch.device("cuda", 0)
         self.calc = d3.D3(table, mode=mode, skin=skin, **prm)
         self.calc.build(system["pos"], system["types"], system["cell"], system["pbc"])
-        self.cell = np.ascontiguousarray(system["cell"], dtype=np.float64)
-        self.pbc = np.ascontiguousarray(system["pbc"], dtype=np.int32)
         self.n = self.calc.n
         self.out = {"energy": torch.zeros(1, dtype=torch.float64, device=self.dev),
                     "forces": torch.zeros((self.n, 3), dtype=torch.float64, device=self.dev),
@@ -109,16 +107,17 @@ class Runner:
         self.stream = torch.cuda.current_stream()
 
     def step(self, rebuild=True):
+        """One step: with rebuild, the neighbour build from the positions
+        (D3_REBUILD, as for a new configuration), then the evaluation."""
         d3, c = self.d3, self.calc
-        if rebuild:
-            d3.d3_build_neighbors(c.ctx, c.pos, c.types, self.cell, self.pbc, self.stream)
+        fl = d3.D3_REBUILD if rebuild else 0
         if self.per_atom:
             o = self.out
             d3.d3_evaluate(c.ctx, c.pos, o["energy"], o["forces"], o["virial"], None,
-                           o["atom_virial"], self.vel, o["heat_current"], 0, self.stream)
+                           o["atom_virial"], self.vel, o["heat_current"], fl, self.stream)
         else:
             d3.d3_energy_forces_virial(c.ctx, c.pos, self.out["energy"], self.out["forces"],
-                                       self.out["virial"], None, 0, self.stream)
+                                       self.out["virial"], None, fl, self.stream)
 
     def timed(self, steps, warmup, rebuild=True):
         torch = self.torch

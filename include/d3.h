@@ -40,7 +40,8 @@
  *    and the same call in the same mode have completed on the context
  *    (so that every buffer exists), d3_build_neighbors, d3_coordination,
  *    d3_energy_forces_virial and d3_evaluate (n > 0, flags without
- *    D3_AUTO_REBUILD, timing off) enqueue kernels only: no allocation,
+ *    D3_AUTO_REBUILD, timing off; D3_REBUILD allowed) enqueue kernels
+ *    only: no allocation,
  *    memset, copy or synchronisation, so they may be captured and the
  *    graph replayed on new positions written into the same buffers.
  *    d3_status, d3_list_stats, the first build of a geometry and
@@ -92,6 +93,12 @@ typedef enum d3_mode {
 #define D3_AUTO_REBUILD 2u /* rebuild the neighbour lists first if any atom
                               moved more than skin/2 since the last build
                               (synchronises the stream once) */
+#define D3_REBUILD 4u      /* rebuild the neighbour lists from pos first, as
+                              d3_build_neighbors would with the species, cell
+                              and pbc of the last build, without a
+                              synchronisation: one call per new configuration
+                              (single-point evaluations).  List overflow is
+                              then reported by d3_status, as after a build */
 
 /* Damping parameters (Eq. 2) and cutoffs.  a2, r_pot, r_cn, skin in
  * Angstrom; s6, a1, s8 dimensionless.  Requires r_pot > 0, r_cn > 0,
@@ -168,8 +175,9 @@ int d3_coordination(d3_ctx *ctx, const double *pos, double *cn_out,
  * energy: device double[1]; forces: device double[n*3]; virial: device
  * double[9] row-major; atom_energy: device double[n] or NULL (site
  * energies U_i of Eq. 2).  Any output pointer except energy may be NULL.
- * flags: D3_ACCUMULATE, D3_AUTO_REBUILD.  Errors: STATE, INVALID_ARG,
- * HIP; with D3_AUTO_REBUILD also CAPACITY. */
+ * flags: D3_ACCUMULATE, D3_AUTO_REBUILD, D3_REBUILD (which takes
+ * precedence over D3_AUTO_REBUILD).  Errors: STATE, INVALID_ARG, HIP; with
+ * D3_AUTO_REBUILD also CAPACITY. */
 int d3_energy_forces_virial(d3_ctx *ctx, const double *pos, double *energy,
                             double *forces, double *virial,
                             double *atom_energy, uint32_t flags,

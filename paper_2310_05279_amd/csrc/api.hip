@@ -697,7 +697,8 @@ static int run_evaluate(d3_ctx* c, const double* pos, const d3_outputs& o, uint3
     if (o.heat_current && !o.velocities)
         return fail(D3_ERR_INVALID_ARG, "heat_current needs velocities");
     if (c->n > 0 && !pos) return fail(D3_ERR_INVALID_ARG, "pos is NULL");
-    if (flags & ~(D3_ACCUMULATE | D3_AUTO_REBUILD)) return fail(D3_ERR_INVALID_ARG, "unknown flags");
+    if (flags & ~(D3_ACCUMULATE | D3_AUTO_REBUILD | D3_REBUILD))
+        return fail(D3_ERR_INVALID_ARG, "unknown flags");
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
     const int acc = (flags & D3_ACCUMULATE) ? 1 : 0;
@@ -709,8 +710,16 @@ static int run_evaluate(d3_ctx* c, const double* pos, const d3_outputs& o, uint3
         }
         return D3_OK;
     }
-    D3CHK(update_positions(c, pos, s));
-    if (flags & D3_AUTO_REBUILD) {
+    if (flags & D3_REBUILD) {
+        // a build from pos writes the sorted positions itself, so the
+        // per-evaluation position update is not needed
+        int32_t pbc[3];
+        for (int k = 0; k < 3; k++) pbc[k] = c->geo.pbc[k];
+        D3CHK(build(c, c->n, pos, c->type_copy.as<int32_t>(), c->cell, pbc, s));
+    } else {
+        D3CHK(update_positions(c, pos, s));
+    }
+    if ((flags & D3_AUTO_REBUILD) && !(flags & D3_REBUILD)) {
         int st = 0;
         D3CHK(read_status(c, s, &st));
         if (st & (ST_STALE | ST_CAPACITY)) {

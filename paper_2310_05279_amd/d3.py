@@ -34,6 +34,7 @@ MODES = {"plain": 0, "prec": 1, "surrogate": 2, "literal": 3}
 
 D3_ACCUMULATE = 1
 D3_AUTO_REBUILD = 2
+D3_REBUILD = 4
 D3_MAX_REF = 5
 D3_MAX_ELEM = 16
 D3_MLP_PARAMS = 1251

@@ -23,10 +23,11 @@ def _capture(calc, system, out, build, stream):
     pbc = np.ascontiguousarray(system["pbc"], dtype=np.int32)
 
     def step():
-        if build:
+        if build == "call":
             d3.d3_build_neighbors(calc.ctx, calc.pos, calc.types, cell, pbc, stream)
+        flags = d3.D3_REBUILD if build == "flag" else 0
         d3.d3_energy_forces_virial(calc.ctx, calc.pos, out["energy"], out["forces"],
-                                   out["virial"], out["atom_energy"], 0, stream)
+                                   out["virial"], out["atom_energy"], flags, stream)
 
     with torch.cuda.stream(stream):
         for _ in range(3):
@@ -41,9 +42,10 @@ def _capture(calc, system, out, build, stream):
 
 
 @pytest.mark.parametrize("mode,build,skin,scale", [
-    ("plain", True, 0.0, 0.05),
-    ("prec", True, 0.0, 0.05),
-    ("plain", False, 1.0, 0.1),
+    ("plain", "call", 0.0, 0.05),
+    ("prec", "call", 0.0, 0.05),
+    ("plain", "flag", 0.0, 0.05),
+    ("plain", None, 1.0, 0.1),
 ])
 def test_graph_replays_match_eager(mode, build, skin, scale):
     import torch

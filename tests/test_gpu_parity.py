@@ -384,6 +384,38 @@ def test_skin_reuse_stale_and_auto_rebuild():
     calc.close()
 
 
+def test_rebuild_flag():
+    """D3_REBUILD rebuilds the lists from the given positions before the
+    evaluation: after large moves it gives bit for bit what a fresh build
+    and evaluation give, alone or together with the other flags, and the
+    build counts as one (no position update follows it)."""
+    import torch
+    from paper_2310_05279_amd import d3
+    m = synth.mof_like(2000, seed=41)
+    n = m["pos"].shape[0]
+    calc = d3.D3(TAB, skin=0.5)
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    rng = np.random.default_rng(3)
+    for rep, flags in enumerate((d3.D3_REBUILD, d3.D3_REBUILD | d3.D3_AUTO_REBUILD)):
+        pos = m["pos"] + rng.uniform(-0.6, 0.6, size=(n, 3))  # beyond half the skin
+        got = calc.compute(pos, flags=flags)
+        ref = d3.D3(TAB, skin=0.5)
+        ref.build(pos, m["types"], m["cell"], m["pbc"])
+        exp = ref.compute(pos)
+        torch.cuda.synchronize()
+        calc.status()
+        for k in ("energy", "forces", "virial", "atom_energy"):
+            assert torch.equal(got[k], exp[k]), "flags %d: %s differs" % (flags, k)
+        ref.close()
+        print("rebuild flag %d: bitwise equal to a fresh build" % flags, flush=True)
+    r = R.d3(pos, m["types"], m["cell"], m["pbc"], TAB)
+    assert abs(float(got["energy"].cpu()[0]) - r["energy"]) / n <= 1e-6
+    acc = calc.compute(pos, flags=d3.D3_REBUILD | d3.D3_ACCUMULATE, out=got)
+    torch.cuda.synchronize()
+    assert torch.allclose(acc["forces"], 2 * exp["forces"], rtol=1e-14, atol=0)
+    calc.close()
+
+
 def test_bad_species_reported_and_contained():
     torch = _torch()
     from paper_2310_05279_amd import d3
