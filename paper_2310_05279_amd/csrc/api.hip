@@ -502,7 +502,6 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
     D3CHK(run_build(c, pos, type, !same, s));
     phase_mark(c, PH_BUILD, s);
     c->built = true;
-    c->fresh_build = true;
     c->last_stream = s;
     return D3_OK;
 }

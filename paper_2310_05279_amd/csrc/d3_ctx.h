@@ -57,7 +57,6 @@ struct d3_ctx {
     double cell[9] = {};
     d3::Geo geo{};
     bool built = false;
-    bool fresh_build = false;
     bool counts_clean = false;  // bin counts and scatter cursors are zero
     // cell-sorted data
     d3::Buf bin_of, shift, count, bin_start, scan_tmp, perm_tmp, perm, slab;
