@@ -416,6 +416,32 @@ def test_rebuild_flag():
     calc.close()
 
 
+def test_mode_switch_on_one_context():
+    """Switching the mode of one context between evaluations (plain,
+    precision, literal, plain, with and without per-atom virials) gives,
+    bit for bit, what a fresh context in each mode gives."""
+    import torch
+    from paper_2310_05279_amd import d3
+    m = synth.mof_like(1200, seed=17)
+    calc = d3.D3(TAB)
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    for mode in ("plain", "prec", "literal", "plain", "prec"):
+        calc.set_mode(mode)
+        for av in (False, True):
+            got = calc.compute(atom_virial=av)
+            ref = d3.D3(TAB, mode=mode)
+            ref.build(m["pos"], m["types"], m["cell"], m["pbc"])
+            exp = ref.compute(atom_virial=av)
+            torch.cuda.synchronize()
+            calc.status()
+            for k in exp:
+                if exp[k] is not None:
+                    assert torch.equal(got[k], exp[k]), "%s (atom_virial=%s): %s" % (mode, av, k)
+            ref.close()
+        print("mode %s after a switch: bitwise equal to a fresh context" % mode, flush=True)
+    calc.close()
+
+
 def test_bad_species_reported_and_contained():
     torch = _torch()
     from paper_2310_05279_amd import d3
