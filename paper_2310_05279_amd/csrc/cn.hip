@@ -102,10 +102,10 @@ k_cn(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_t
                 else if (rl == 7) *(double*)p1 = pv;
                 else if (rl == 8) ((int*)p2)[3] = zi;
             } else {
-                // slot s (x, y, z, w0..w4) is double s % 4 of piece s / 4
-                const int s = rl < MAXREF ? 3 + rl : rl - 5;
+                // slot (x, y, z, w0..w4 = 0..7) is double slot % 4 of piece slot / 4
+                const int slot = rl < MAXREF ? 3 + rl : rl - 5;
                 const double v = rl < MAXREF ? (((zi >> rl) & 1) && rl < 4 ? -wl : wl) : pv;
-                if (rl < 8) W[piece_at(NPIECE, PBLK, s >> 2, i) * 4 + (s & 3)] = v;
+                if (rl < 8) W[piece_at(NPIECE, PBLK, slot >> 2, i) * 4 + (slot & 3)] = v;
             }
         }
     }
