@@ -205,19 +205,24 @@ def pair_terms(r2, zi, zj, c6, tab, prm):
     return phi, dphi_r, dphi_dc6
 
 
-def d3(pos, types, cell, pbc, table, prm=None):
+def d3(pos, types, cell, pbc, table, prm=None, c6_fn=None):
     """Full FP64 evaluation.  Returns dict with energy, forces (N,3),
-    virial (3,3), atom_energy (N), cn (N), dE/dn (N)."""
+    virial (3,3), atom_energy (N), cn (N), dE/dn (N).
+
+    c6_fn(zi, zj, ni, nj) -> (C6, dC6/dn_i, dC6/dn_j), arrays over the
+    dispersion entries, replaces Eq. 3 when given (in eV A^6); the rest of
+    the evaluation is unchanged.  It lets a test feed another C6 model, such
+    as the learned surrogate, through the same Eqs. 1-7."""
     prm = prm or Params()
     tab = convert_table(table)
     pos = np.asarray(pos, dtype=np.float64)
     types = np.asarray(types, dtype=np.int64)
     n = pos.shape[0]
     i, j, d = entries(pos, cell, pbc, max(prm.r_pot, prm.r_cn))
-    return _evaluate(n, types, tab, prm, i, j, d)
+    return _evaluate(n, types, tab, prm, i, j, d, c6_fn=c6_fn)
 
 
-def _evaluate(n, types, tab, prm, i, j, d, cn=None):
+def _evaluate(n, types, tab, prm, i, j, d, cn=None, c6_fn=None):
     r2 = np.einsum("ek,ek->e", d, d)
     if cn is None:
         cn = coordination(n, types, tab, i, j, d, prm.r_cn)
@@ -225,7 +230,10 @@ def _evaluate(n, types, tab, prm, i, j, d, cn=None):
     mp = r2 < prm.r_pot * prm.r_pot
     ip, jp, dp, r2p = i[mp], j[mp], d[mp], r2[mp]
     zi, zj = types[ip], types[jp]
-    c6, dci, _ = c6_eq3(zi, zj, cn[ip], cn[jp], tab)
+    if c6_fn is None:
+        c6, dci, _ = c6_eq3(zi, zj, cn[ip], cn[jp], tab)
+    else:
+        c6, dci, _ = c6_fn(zi, zj, cn[ip], cn[jp])
     phi, dphi_r, dphi_dc6 = pair_terms(r2p, zi, zj, c6, tab, prm)
     atom_e = 0.5 * np.bincount(ip, weights=phi, minlength=n)
     dedn = np.bincount(ip, weights=dphi_dc6 * dci, minlength=n)

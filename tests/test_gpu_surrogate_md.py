@@ -211,6 +211,70 @@ def test_surrogate_forces_against_oracle(trained):
     calc.close()
 
 
+def _network_c6(w, cn_hi):
+    """C6 and its two CN derivatives from the FP64 forward of the trained
+    network (per element pair, inputs 2 n / cn_hi - 1, outputs
+    de-standardised), exact Eq. 3 outside the trained box: the C6 model the
+    surrogate pass evaluates, for the oracle's c6_fn."""
+    tabc = O.convert_table(TAB)
+    pairs = _pairs()
+
+    def fn(zi, zj, ni, nj):
+        c6, dci, dcj = O.c6_eq3(zi, zj, ni, nj, tabc)
+        inb = (ni <= cn_hi) & (nj <= cn_hi)
+        for p, (e, f) in enumerate(pairs):
+            theta = w[p * M.N_PARAMS:(p + 1) * M.N_PARAMS].astype(np.float64)
+            st = w[NP * M.N_PARAMS + 6 * p: NP * M.N_PARAMS + 6 * p + 6].astype(np.float64)
+            for sw in ((False,) if e == f else (False, True)):
+                sel = inb & ((zi == f) & (zj == e) if sw else (zi == e) & (zj == f))
+                if not sel.any():
+                    continue
+                xa, xb = 2.0 * ni[sel] / cn_hi - 1.0, 2.0 * nj[sel] / cn_hi - 1.0
+                y, _ = M.forward(theta, np.stack([xb, xa] if sw else [xa, xb], axis=1))
+                y = y * st[3:] + st[:3]
+                c6[sel] = y[:, 0]
+                dci[sel] = y[:, 2] if sw else y[:, 1]
+                dcj[sel] = y[:, 1] if sw else y[:, 2]
+        return c6, dci, dcj
+
+    return fn
+
+
+def test_surrogate_pass_matches_oracle_with_the_network(trained):
+    """Parity of the surrogate dispersion pass itself: the FP64 oracle fed
+    the same trained network as its C6 model (and exact Eq. 3 outside the
+    box) gives the energy, forces and virial of the surrogate mode to the
+    precision-form gates; what remains is the BF16-split inference and the
+    FP32 pair arithmetic."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    w = trained["w"]
+    m = synth.mof_like(1000, density=0.06, seed=58)  # a few CNs beyond the box
+    cn_hi = float(w[-1])
+    ref = O.d3(m["pos"], m["types"], m["cell"], m["pbc"], TAB, c6_fn=_network_c6(w, cn_hi))
+    # no coordination number so close to the box edge that FP32 rounding could
+    # take the other side of the fallback test
+    assert np.abs(ref["cn"] - cn_hi).min() > 1e-4
+    n_out = int((ref["cn"] > cn_hi).sum())
+    calc = d3.D3(TAB, mode="surrogate")
+    d3.d3_c6_surrogate_set_weights(calc.ctx, w)
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    out = calc.compute()
+    torch.cuda.synchronize()
+    calc.status()
+    n = m["pos"].shape[0]
+    de = abs(out["energy"].item() - ref["energy"]) / n
+    df = np.abs(out["forces"].cpu().numpy() - ref["forces"]).max()
+    dw = np.abs(out["virial"].cpu().numpy() - ref["virial"]).max()
+    print("surrogate pass vs oracle with the network (%d atoms outside the box): "
+          "|dE|/atom=%.2e max|dF|=%.2e max|dW|=%.2e (max|W| %.2e)"
+          % (n_out, de, df, dw, np.abs(ref["virial"]).max()), flush=True)
+    assert n_out > 0, "the cell should exercise the exact fallback"
+    assert de <= 1e-6 and df <= 1e-4
+    assert dw <= 1e-5 * np.abs(ref["virial"]).max()
+    calc.close()
+
+
 def test_surrogate_pass_with_long_lists(trained):
     """Lists longer than one LDS chunk of the surrogate pass (a 2 A skin puts
     about 460 entries in each row) give the same energy, forces and virial
