@@ -285,7 +285,7 @@ def energy_only(pos, types, cell, pbc, table, prm=None):
     return 0.5 * phi.sum()
 
 
-def sampled(pos, types, cell, pbc, table, idx, prm=None):
+def sampled(pos, types, cell, pbc, table, idx, prm=None, c6_fn=None):
     """Forces, site energies, per-atom virials, coordination numbers and
     dE/dn of the atoms ``idx`` of a large cell, each computed from its own
     neighbourhood.
@@ -294,9 +294,12 @@ def sampled(pos, types, cell, pbc, table, idx, prm=None):
     j within R_cn of k; dE/dn_j depends on n_l for l within R_pot of j, and
     n_l on atoms within R_cn of l.  So every quantity needed for atom k is
     fixed by the images within R_pot + 2 R_cn of k, and the full definition
-    restricted to that ball gives the exact result."""
+    restricted to that ball gives the exact result.  c6_fn: as in d3()."""
     prm = prm or Params()
     tab = convert_table(table)
+    if c6_fn is None:
+        def c6_fn(zi, zj, ni, nj):
+            return c6_eq3(zi, zj, ni, nj, tab)
     pos = np.asarray(pos, dtype=np.float64)
     types = np.asarray(types, dtype=np.int64)
     rbig = prm.r_pot + 2.0 * prm.r_cn + 1e-6
@@ -336,7 +339,7 @@ def sampled(pos, types, cell, pbc, table, idx, prm=None):
             m = rr < prm.r_pot * prm.r_pot
             m[a] = False
             zi = np.full(int(m.sum()), lt[a])
-            c6, dci, _ = c6_eq3(zi, lt[m], np.full(zi.size, cn[a]), cn[m], tab)
+            c6, dci, _ = c6_fn(zi, lt[m], np.full(zi.size, cn[a]), cn[m])
             _, _, dphi_dc6 = pair_terms(rr[m], zi, lt[m], c6, tab, prm)
             g[a] = (dphi_dc6 * dci).sum()
         # force and site energy of k
@@ -345,7 +348,7 @@ def sampled(pos, types, cell, pbc, table, idx, prm=None):
         m = rr < prm.r_pot * prm.r_pot
         m[me] = False
         zi = np.full(int(m.sum()), lt[me])
-        c6, _, _ = c6_eq3(zi, lt[m], np.full(zi.size, cn[me]), cn[m], tab)
+        c6, _, _ = c6_fn(zi, lt[m], np.full(zi.size, cn[me]), cn[m])
         phi, dphi_r, _ = pair_terms(rr[m], zi, lt[m], c6, tab, prm)
         f = (dphi_r[:, None] * dd[m]).sum(0)
         w = -0.5 * np.einsum("e,ea,eb->ab", dphi_r, dd[m], dd[m])

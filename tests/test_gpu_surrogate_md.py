@@ -275,6 +275,32 @@ def test_surrogate_pass_matches_oracle_with_the_network(trained):
     calc.close()
 
 
+def test_surrogate_full_size_sampled(trained):
+    """The 200 000-atom MOF-like cell in surrogate mode, in the launch shape
+    the bench times: sampled atoms' forces and site energies against the
+    sampled oracle fed the same network."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    w = trained["w"]
+    cn_hi = float(w[-1])
+    m = synth.mof_like(200_000)
+    calc = d3.D3(TAB, mode="surrogate")
+    d3.d3_c6_surrogate_set_weights(calc.ctx, w)
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    out = calc.compute()
+    torch.cuda.synchronize()
+    calc.status()
+    idx = np.random.default_rng(21).choice(m["pos"].shape[0], 6, replace=False)
+    ref = O.sampled(m["pos"], m["types"], m["cell"], m["pbc"], TAB, idx,
+                    c6_fn=_network_c6(w, cn_hi))
+    df = np.abs(out["forces"].cpu().numpy()[idx] - ref["forces"]).max()
+    du = np.abs(out["atom_energy"].cpu().numpy()[idx] - ref["atom_energy"]).max()
+    print("surrogate 200k sampled vs oracle with the network: max|dF|=%.2e max|dU_i|=%.2e"
+          % (df, du), flush=True)
+    assert df <= 1e-4 and du <= 1e-6
+    calc.close()
+
+
 def test_surrogate_pass_with_long_lists(trained):
     """Lists longer than one LDS chunk of the surrogate pass (a 2 A skin puts
     about 460 entries in each row) give the same energy, forces and virial
