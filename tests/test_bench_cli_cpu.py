@@ -1,0 +1,56 @@
+"""Host-side checks of bench.py that need no GPU: the one-GPU contract and
+the pieces of the JSON line computed on the host."""
+
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    """The path is single-GPU: asking for several GPUs (or running under a
+    multi-rank launcher) exits with status 2 and says why, before any GPU
+    work."""
+    for args, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "4"})):
+        e = dict(os.environ, **env)
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + args,
+                           capture_output=True, text=True, env=e, timeout=120)
+        assert r.returncode == 2
+        assert "one GPU" in r.stderr
+        assert r.stdout == ""
+
+
+def test_flops_per_pair_and_unique_pair_count():
+    """The roofline's algorithmic count: 56 + 3 (K_i + K_j) flops per unique
+    pair, summed over the unique pairs within R_pot, which the k-d tree
+    must count exactly as the oracle's brute force over images does."""
+    import bench
+    import synth
+    from oracle import d3_oracle as O
+    assert bench._flops_per_pair(1, 1) == 62.0
+    assert bench._flops_per_pair(5, 3) == 80.0
+    table = synth.make_table()
+    m = synth.mof_like(1200, seed=19)  # a 31 A cube: one image per pair within 12 A
+    flops, pairs = bench.algorithmic_pair_flops(m, table, 12.0)
+    i, j, d = O.entries(m["pos"], m["cell"], m["pbc"], 12.0)
+    assert 2 * pairs == i.size
+    k = np.asarray(table["n_ref"])[m["types"]]
+    assert flops == 0.5 * np.sum(56.0 + 3.0 * (k[i] + k[j]))
+
+
+def test_pair_traffic_figure_is_tied_to_the_kernel_sources():
+    """The HBM traffic figure is reported only while the dispersion-pass
+    sources it was measured on are unchanged."""
+    import bench
+    t = bench.PAIR_TRAFFIC
+    got = bench.pair_traffic_bytes()
+    if bench._sources_hash(t["sources"]) == t["sha256"]:
+        want = 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+        assert got == want and got > 0
+    else:
+        assert got is None
+    assert np.isfinite(t["fetch_scale"]) and t["fetch_scale"] > 0
