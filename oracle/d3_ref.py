@@ -34,11 +34,13 @@ def _load():
         P = ctypes.c_void_p
         D = ctypes.c_double
         I = ctypes.c_int
-        lib.d3ref_evaluate.restype = ctypes.c_long
-        lib.d3ref_evaluate.argtypes = [I, P, P, P, P, I, P, P, P, P, P,
-                                       D, D, D, D, D, D, I,
-                                       P, P, P, P, P, P, P]
+        lib.d3ref_evaluate_mode.restype = ctypes.c_long
+        lib.d3ref_evaluate_mode.argtypes = [I, P, P, P, P, I, P, P, P, P, P,
+                                            D, D, D, D, D, D, I, I, I,
+                                            P, P, P, P, P, P, P]
         lib.d3ref_threads.restype = I
+        lib.d3ref_threads_for.restype = I
+        lib.d3ref_threads_for.argtypes = [I]
         _lib = lib
     return _lib
 
@@ -47,14 +49,21 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 
 
-def threads():
-    return _load().d3ref_threads()
+def threads(n_threads=0):
+    """OpenMP threads an evaluation with n_threads uses (0: all)."""
+    return _load().d3ref_threads_for(int(n_threads))
 
 
 def d3(pos, types, cell, pbc, table, s6=1.0, a1=0.4289, s8=0.7875, a2=4.4407,
-       r_pot=12.0, r_cn=6.0, n_threads=0):
+       r_pot=12.0, r_cn=6.0, n_threads=0, cells=False, n_eval=None):
     """Full FP64 evaluation; returns the same dict layout as
-    d3_oracle.d3 plus the number of dispersion entries."""
+    d3_oracle.d3 plus the number of dispersion entries.  cells=False finds
+    the entries by brute force over every atom and lattice translation;
+    cells=True from cell lists (the same entries, in O(n) time and memory:
+    the mode for large cells).  n_threads=0 uses every OpenMP thread.
+    n_eval (cell-list mode, timing only): run each pass for the first n_eval
+    atoms alone, the work of n_eval atoms of the cell; the results are then
+    not the cell's."""
     lib = _load()
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     n = pos.shape[0]
@@ -74,10 +83,13 @@ def d3(pos, types, cell, pbc, table, s6=1.0, a1=0.4289, s8=0.7875, a2=4.4407,
     cn = np.zeros(n)
     g = np.zeros(n)
     av = np.zeros((n, 3, 3))
-    total = lib.d3ref_evaluate(
+    if cells and cellp is None:
+        raise ValueError("the cell-list mode needs a cell")
+    total = lib.d3ref_evaluate_mode(
         n, _ptr(pos), _ptr(types), _ptr(cellp), _ptr(pbcp), ne, _ptr(n_ref),
         _ptr(cn_ref), _ptr(c6), _ptr(rcov), _ptr(r2r4), s6, a1, s8, a2,
-        r_pot, r_cn, int(n_threads), _ptr(energy), _ptr(forces),
+        r_pot, r_cn, int(n_threads), 1 if cells else 0,
+        n if n_eval is None else int(n_eval), _ptr(energy), _ptr(forces),
         _ptr(virial), _ptr(ae), _ptr(cn), _ptr(g), _ptr(av))
     if total < 0:
         raise MemoryError("d3ref_evaluate failed")

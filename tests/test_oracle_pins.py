@@ -578,6 +578,65 @@ def test_c_oracle_matches_numpy_oracle():
             assert np.abs(a[k] - b[k]).max() <= tol * sc, k
 
 
+def _random_cell(rng, lo, hi, skew):
+    """A random triclinic cell: rows a, b, c with lengths in [lo, hi] and
+    off-diagonal parts up to skew times the diagonal."""
+    cell = np.diag(rng.uniform(lo, hi, 3))
+    cell[1, 0] = skew * rng.uniform(-1, 1) * cell[1, 1]
+    cell[2, 0] = skew * rng.uniform(-1, 1) * cell[2, 2]
+    cell[2, 1] = skew * rng.uniform(-1, 1) * cell[2, 2]
+    return cell
+
+
+def _brute_vs_cells(c, tab, **prm):
+    a = R.d3(c["pos"], c["types"], c["cell"], c["pbc"], tab, **prm)
+    b = R.d3(c["pos"], c["types"], c["cell"], c["pbc"], tab, cells=True, **prm)
+    assert b["n_entries"] == a["n_entries"]
+    assert b["energy"] == pytest.approx(a["energy"], rel=1e-12, abs=1e-300)
+    for k in ("forces", "virial", "atom_energy", "atom_virial", "cn", "dedn"):
+        # forces that cancel by symmetry (one atom and its images) are
+        # rounding noise: scale them by the energy, eV per Angstrom
+        sc = max(np.abs(a[k]).max(), abs(a["energy"]), 1e-30)
+        tol = 1e-10 if k == "dedn" else 1e-12
+        assert np.abs(a[k] - b[k]).max() <= tol * sc, k
+    return a
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_cell_list_mode_matches_brute_force_small_cells(seed):
+    """The oracle's cell-list mode (used for the 10^5-10^6-atom cells)
+    finds exactly the entries of the brute-force mode and gives the same
+    results, on tiny skewed cells whose lattice planes lie closer than the
+    cutoffs (several images of one atom, and the same bin visited with
+    different images), with atoms outside the cell, and with open axes.  A
+    stencil one bin too short, a wrong image of a wrapped bin or a missed
+    self-image would change the entry count."""
+    rng = np.random.default_rng(100 + seed)
+    tab = _table()
+    cell = _random_cell(rng, 4.0, 9.0, 0.4)
+    n = int(rng.integers(1, 9))
+    pbc = [(1, 1, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 0, 0), (0, 0, 0)][seed]
+    s = rng.uniform(-0.3, 1.3, (n, 3))
+    c = {"pos": s @ cell, "types": rng.integers(0, 5, n).astype(np.int32), "cell": cell,
+         "pbc": np.array(pbc)}
+    a = _brute_vs_cells(c, tab, r_pot=12.0, r_cn=6.0)
+    if sum(pbc) == 3 and n > 1:
+        assert a["n_entries"] > 20 * n  # many images per atom
+
+
+def test_cell_list_mode_matches_brute_force_mid_cells():
+    """Cells between two and three cutoffs wide (two bins per axis: both
+    neighbouring offsets reach the other bin, with different images),
+    unequal cutoffs and a cutoff above the box, on a MOF-like cube and on
+    the bilayer."""
+    tab = _table()
+    m = synth.mof_like(700, seed=9)  # L = 25.96 A
+    _brute_vs_cells(m, tab, r_pot=12.0, r_cn=6.0)
+    _brute_vs_cells(m, tab, r_pot=9.0, r_cn=9.5)
+    g = synth.bilayer_graphene()
+    _brute_vs_cells(g, tab, r_pot=16.0, r_cn=5.0)
+
+
 def test_sampled_mode_matches_full():
     """The per-atom neighbourhood evaluation used at 10^5-10^6 atoms gives
     the same force, site energy, CN and dE/dn as the full evaluation."""
@@ -637,6 +696,33 @@ def test_mlp_oracle_closed_forms():
     assert y[0] == pytest.approx([0.5 + s, -1.0, 2.0 - 2.0 * s], rel=1e-14)
     assert M.silu(np.array([0.0]))[0] == 0.0
     assert M.silu(np.array([40.0]))[0] == pytest.approx(40.0, rel=1e-15)
+
+
+def test_adam_first_steps_closed_form():
+    """Adam (one update per step, step counted from 1) against its closed
+    form for the first two steps, from zero moments: with gradient g1 then
+    g2 the bias-corrected moments are g1, g1^2 after step 1 and
+    (b1 g1 + g2)/(1 + b1), (b2 g1^2 + g2^2)/(1 + b2) after step 2, so the
+    updates are -lr g1/(|g1| + eps) and -lr m2/(sqrt(v2) + eps).  A bias
+    correction from step 0, swapped betas or a missing square root fail
+    this."""
+    from oracle import mlp_oracle as M
+    rng = np.random.default_rng(4)
+    theta = rng.normal(size=40)
+    g1 = rng.normal(size=40)
+    g2 = rng.normal(size=40) * rng.uniform(0.1, 3.0, 40)
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    z = np.zeros(40)
+    t1, m, v = M.adam_step(theta, g1, z, z, 1, lr)
+    assert t1 - theta == pytest.approx(-lr * g1 / (np.abs(g1) + eps), rel=1e-12)
+    t2, m, v = M.adam_step(t1, g2, m, v, 2, lr)
+    mh = (b1 * g1 + g2) / (1 + b1)
+    vh = (b2 * g1 * g1 + g2 * g2) / (1 + b2)
+    assert t2 - t1 == pytest.approx(-lr * mh / (np.sqrt(vh) + eps), rel=1e-10)
+    # a constant gradient moves every parameter by lr per step (eps aside)
+    t3, m3, v3 = M.adam_step(theta, g1, z, z, 1, lr)
+    t4, _, _ = M.adam_step(t3, g1, m3, v3, 2, lr)
+    assert t4 - t3 == pytest.approx(-lr * np.sign(g1), rel=1e-6)
 
 
 # ----------------------------------------------- velocity-Verlet driver ----
