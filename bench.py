@@ -4,14 +4,17 @@ One step = one pass of the whole path on one batch of input: neighbour
 build (binning, counting sort, both lists), coordination numbers and
 Gaussian weights, the dispersion pass, the chain pass and the FP64
 reductions, i.e. energy, forces and virial of the cell.  The headline
-workload is the 24 000-atom MOF-like cell (H,C,N,O,Zn 4:6:1:2:1 at 0.04
-atoms/A^3, R_pot = 12 A, R_cn = 6 A) in the plain FP64 form; inputs are
-resident in HBM before timing starts.  Extra fields report the FP32
-precision form and the learned-C6 surrogate form on the same cell (with
-their force deviation from the plain form), the evaluation alone (lists
-reused as in MD), the 200 000-atom and 10^6-atom MOF-like cells, the
-500 000-atom bilayer, and velocity-Verlet NVE on the 10^6-atom cell (300 K,
-1 fs, 1 A skin) in all three forms with its total-energy drift.
+workload is the 10^6-atom MOF-like cell (H,C,N,O,Zn 4:6:1:2:1 at 0.04
+atoms/A^3, R_pot = 12 A, R_cn = 6 A), the largest single-GPU configuration,
+in the plain FP64 form, with the neighbour build in every step; inputs are
+resident in HBM before timing starts.  The roofline object is the
+dispersion pass's (k_pair) against the FP64 vector peak, with the
+algorithmic flops of every unique pair within R_pot; a second entry puts
+the list kernel (k_list) against the HBM peak.  The CPU baseline is the C
+oracle's cell-list mode on the same cell (all host cores; a single-thread
+sample beside it).  Extra fields report the precision and surrogate forms,
+Eq. 3 as printed, the 24 000- and 200 000-atom cells, the 500 000-atom
+bilayer, long cutoffs and velocity-Verlet NVE.
 
 Prints ONE JSON line.  Usage: python bench.py [--steps K] [--warmup W]
 """
@@ -34,15 +37,12 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
-# HBM bytes per launch of the dispersion pass on the 24 000-atom cell, from
-# two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
+# HBM bytes per launch of the dispersion pass on the 10^6-atom cell, from two
+# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch), each scaled by what the same counter read for a 512 MiB device
-# copy (FETCH_SIZE x 1.9999, WRITE_SIZE x 1.0000).  The figure belongs to the
-# kernel sources it was taken with: when their hash differs it is not used.
-PAIR_TRAFFIC = {"fetch_kib": 24113.404, "write_kib": 1019.159,
-                "fetch_scale": 1.9999, "write_scale": 1.0,
-                "sources": ("disp.hip", "d3_device.h", "d3_internal.h"),
-                "sha256": "6158d49da765c79d829e52b29433002a"}
+# copy.  The figure belongs to the kernel sources it was taken with: when
+# their hash differs it is not used (None: not measured on these sources).
+PAIR_TRAFFIC = None
 
 
 def _sources_hash(names):
@@ -54,32 +54,52 @@ def _sources_hash(names):
     return h.hexdigest()[:32]
 
 
-def pair_traffic_bytes():
-    t = PAIR_TRAFFIC
-    if _sources_hash(t["sources"]) != t["sha256"]:
+def pair_traffic_bytes(t=None):
+    t = PAIR_TRAFFIC if t is None else t
+    if t is None or _sources_hash(t["sources"]) != t["sha256"]:
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
 def _flops_per_pair(ki, kj):
-    """FP64 operations of one unique dispersion pair within R_pot (energy,
-    both forces, virial, both dE/dn terms): 56 for the distance, damping,
-    force and virial arithmetic plus 3 (K_i + K_j) for C6, dC6/dn_i and
-    dC6/dn_j from the factorised weights."""
-    return 56.0 + 3.0 * (ki + kj)
+    """Algorithmic FP64 operations of one unique dispersion pair within
+    R_pot (energy, both forces, virial and both dE/dn terms): 56 for the
+    distance, damping, force and virial arithmetic, 4 K_i K_j for the
+    bilinear form C6 = w_i^T M w_j with its two CN derivatives, and
+    2 K_i + 4 K_j for the weight terms of the atom that evaluates the pair
+    and of its partner, averaged over the two ends of the unordered pair:
+    56 + 4 K_i K_j + 3 (K_i + K_j).  Divisions count as one."""
+    return 56.0 + 4.0 * ki * kj + 3.0 * (ki + kj)
+
+
+def unique_pair_counts(system, r_pot):
+    """Unique pairs (i < j, images included) within r_pot per element pair
+    (e <= f) of a cubic periodic cell: {(e, f): count}.  Input statistics
+    only (k-d trees over the wrapped positions)."""
+    from scipy.spatial import cKDTree
+    box = system["cell"][0, 0]
+    assert np.allclose(system["cell"], np.eye(3) * box) and np.all(system["pbc"])
+    pos = np.mod(system["pos"], box)
+    types = np.asarray(system["types"])
+    els = np.unique(types)
+    trees = {e: cKDTree(pos[types == e], boxsize=box) for e in els}
+    out = {}
+    for a, e in enumerate(els):
+        for f in els[a:]:
+            c = int(trees[e].count_neighbors(trees[f], r_pot))
+            if e == f:
+                c = (c - trees[e].n) // 2
+            out[(int(e), int(f))] = c
+    return out
 
 
 def algorithmic_pair_flops(system, table, r_pot):
-    """Sum of _flops_per_pair over the unique pairs within R_pot of a
-    cubic periodic cell (input statistics only, from a k-d tree)."""
-    from scipy.spatial import cKDTree
-    box = system["cell"][0, 0]
-    tree = cKDTree(np.mod(system["pos"], box), boxsize=box)
-    pairs = tree.query_pairs(r=r_pot, output_type="ndarray")
-    k = np.asarray(table["n_ref"])[system["types"]]
-    ki = k[pairs[:, 0]]
-    kj = k[pairs[:, 1]]
-    return float(np.sum(_flops_per_pair(ki, kj))), int(pairs.shape[0])
+    """Sum of _flops_per_pair over the unique pairs within r_pot, and the
+    number of those pairs."""
+    k = np.asarray(table["n_ref"], dtype=np.float64)
+    counts = unique_pair_counts(system, r_pot)
+    flops = sum(c * _flops_per_pair(k[e], k[f]) for (e, f), c in counts.items())
+    return float(flops), int(sum(counts.values()))
 
 
 class Runner:
@@ -179,7 +199,9 @@ class Runner:
         self.torch.cuda.synchronize()
         t = d3.d3_get_timing(self.calc.ctx)
         d3.d3_set_timing(self.calc.ctx, 0)
-        return {k: (ms / calls if calls else 0.0) for k, (ms, calls) in t.items()}
+        ph = {k: (ms / calls if calls else 0.0) for k, (ms, calls) in t.items()}
+        ph["build"] = ph["sort"] + ph["list"]
+        return ph
 
     def close(self):
         self.calc.close()
@@ -197,28 +219,36 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(system, table):
-    """The C FP64 oracle (brute force over all pairs and images) timed on
-    the host cores for one full E+F+W evaluation of the same cell."""
+def cpu_baseline(system, table, n_threads=0, n_eval=None):
+    """The C FP64 oracle's cell-list mode timed on the host for one E+F+W
+    evaluation of the cell (n_eval: the passes of that many atoms only, a
+    timing sample).  Returns the result, the seconds and the threads."""
     from oracle import d3_ref
     t0 = time.perf_counter()
-    ref = d3_ref.d3(system["pos"], system["types"], system["cell"], system["pbc"], table)
+    ref = d3_ref.d3(system["pos"], system["types"], system["cell"], system["pbc"], table,
+                    cells=True, n_threads=n_threads, n_eval=n_eval)
     dt = time.perf_counter() - t0
-    return ref, dt, d3_ref.threads()
+    return ref, dt, d3_ref.threads(n_threads)
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the precision/surrogate/large-cell/MD fields")
+                    help="skip the precision/surrogate/other-cell/MD fields")
+    ap.add_argument("--no-flops", action="store_true",
+                    help="skip the unique-pair count (roofline fields become null)")
     ap.add_argument("--sur-epochs", type=int, default=300)
     ap.add_argument("--md-steps", type=int, default=200)
-    ap.add_argument("--no-graph", action="store_true",
-                    help="time eager launches only (no HIP graph capture)")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the headline step replayed from a HIP graph")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run 3 plain device-to-device copies of this many MiB "
                          "(a known-size reference for HBM byte counters)")
@@ -241,110 +271,82 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     table = synth.make_table()
-    system = synth.mof_like(24000)
+    system = synth.mof_like(1_000_000)
     n = system["pos"].shape[0]
-    print("[bench] workload mof24000 plain: warmup %d, steps %d" % (args.warmup, args.steps),
-          file=sys.stderr, flush=True)
+    log("workload mof_1M plain: warmup %d, steps %d" % (args.warmup, args.steps))
 
     run = Runner(system, table, "plain")
     ms = run.timed(args.steps, args.warmup)
-    ms_graph = None if args.no_graph else run.graphed(args.steps, args.warmup)
     value = n / (ms * 1e-3)
-    ph = run.phases(max(20, args.steps // 4))
+    ms_graph = run.graphed(args.steps, args.warmup) if args.graph else None
+    ph = run.phases(max(10, args.steps // 2))
     stats = run.calc.stats()
     ms_eval = run.timed(args.steps, 3, rebuild=False)
     res_f = run.out["forces"].cpu().numpy()
     res_e = float(run.out["energy"].item())
     res_w = run.out["virial"].cpu().numpy()
     run.close()
-    print("[bench] plain %.4f ms/step, %s ms as graph replays, phases %s"
-          % (ms, ms_graph, ph), file=sys.stderr, flush=True)
+    log("plain %.4f ms/step, eval only %.4f, phases %s" % (ms, ms_eval, ph))
 
-    flops, npairs = algorithmic_pair_flops(system, table, 12.0)
-    pair_ms = ph["pair"]
-    achieved = flops / (pair_ms * 1e-3) / 1e12
-    roofline = {"kernel": "k_pair<fp64> (dispersion pass)", "bound": "alu",
-                "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": pair_traffic_bytes(),
-                "algorithmic_flops_per_launch": flops, "unique_pairs": npairs,
-                "avg_kernel_ms": pair_ms}
-    if roofline["traffic"] is not None:
-        gbs = roofline["traffic"] / (pair_ms * 1e-3) / 1e9
-        roofline["hbm_GBs"] = gbs
-        roofline["hbm_frac"] = gbs / HBM_PEAK_GBS
+    roofline = None
+    if not args.no_flops:
+        log("counting unique pairs within R_pot per element pair")
+        flops, npairs = algorithmic_pair_flops(system, table, 12.0)
+        pair_ms = ph["pair"]
+        achieved = flops / (pair_ms * 1e-3) / 1e12
+        roofline = {"kernel": "k_pair<fp64> (dispersion pass)", "bound": "alu",
+                    "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": pair_traffic_bytes(),
+                    "algorithmic_flops_per_launch": flops, "unique_pairs": npairs,
+                    "flops_per_unique_pair": flops / npairs, "avg_kernel_ms": pair_ms}
+        if roofline["traffic"] is not None:
+            gbs = roofline["traffic"] / (pair_ms * 1e-3) / 1e9
+            roofline["hbm_GBs"] = gbs
+            roofline["hbm_frac"] = gbs / HBM_PEAK_GBS
+        # the list kernel against HBM: it must read every sorted position
+        # (32 B) and write both lists (4 B per entry) and both counts
+        entries = stats["mean_pot"] * n + stats["mean_cn"] * n
+        list_bytes = 40.0 * n + 4.0 * entries
+        list_gbs = list_bytes / (ph["list"] * 1e-3) / 1e9
+        roofline["other"] = [{"kernel": "k_list (neighbour lists)", "bound": "hbm",
+                              "achieved": list_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": list_gbs / HBM_PEAK_GBS,
+                              "algorithmic_bytes_per_launch": list_bytes,
+                              "avg_kernel_ms": ph["list"]}]
 
-    extra = {"ms_per_step_graph_replay": ms_graph,
-             "ms_per_step_eval_only": ms_eval,
+    extra = {"ms_per_step_eval_only": ms_eval,
              "atom_steps_per_s_eval_only": n / (ms_eval * 1e-3),
+             "ms_per_step_graph_replay": ms_graph,
              "phase_ms": ph, "list_stats": stats}
-    if not args.no_extra:
-        run = Runner(system, table, "prec")
-        ms_p = run.timed(args.steps, args.warmup)
-        php = run.phases(max(20, args.steps // 4))
-        fp = run.out["forces"].cpu().numpy()
-        ep = float(run.out["energy"].item())
-        wp = run.out["virial"].cpu().numpy()
-        run.close()
-        extra["prec_f32"] = {"atom_steps_per_s": n / (ms_p * 1e-3), "ms_per_step": ms_p,
-                             "phase_ms": php,
-                             "pair_frac_fp32_peak": flops / (php["pair"] * 1e-3) / 1e12 /
-                             FP32_VECTOR_PEAK_TFLOPS,
-                             "max_abs_dF_vs_plain": float(np.abs(fp - res_f).max()),
-                             "abs_dE_per_atom_vs_plain": abs(ep - res_e) / n,
-                             "max_abs_dW_vs_plain": float(np.abs(wp - res_w).max())}
-        # per-atom virial (Eq. 7) and heat current (Eq. 8) on top of the plain step
-        run = Runner(system, table, "plain", per_atom=True)
-        ms_a = run.timed(args.steps, args.warmup)
-        pha = run.phases(max(20, args.steps // 4))
-        fa = run.out["forces"].cpu().numpy()
-        run.close()
-        extra["plain_with_atom_virial"] = {
-            "atom_steps_per_s": n / (ms_a * 1e-3), "ms_per_step": ms_a, "phase_ms": pha,
-            "step_time_vs_plain": ms_a / ms, "forces_identical": bool(np.array_equal(fa, res_f))}
-        # learned C6 surrogate: trained on 10^6 exact-labelled CN pairs over the
-        # CN box [0, 99.9th percentile + 0.5]^2 of this cell, then timed
-        from paper_2310_05279_amd import d3 as d3mod
-        run = Runner(system, table, "surrogate")
-        cn = run.calc.coordination().cpu().numpy()
-        cn_hi = float(np.percentile(cn, 99.9) + 0.5)
-        d3mod.d3_c6_surrogate_init(run.calc.ctx, 5)
-        t0 = time.perf_counter()
-        loss = d3mod.d3_c6_surrogate_train(run.calc.ctx, n_samples=1_000_000,
-                                           epochs=args.sur_epochs, lr=5e-3, lr_final=1e-6,
-                                           seed=4, cn_hi=cn_hi)
-        t_train = time.perf_counter() - t0
-        weights = d3mod.d3_c6_surrogate_get_weights(run.calc.ctx)
-        ms_s = run.timed(max(10, args.steps // 4), 3)
-        phs = run.phases(10)
-        fsu = run.out["forces"].cpu().numpy()
-        esu = float(run.out["energy"].item())
-        run.close()
-        extra["surrogate"] = {"atom_steps_per_s": n / (ms_s * 1e-3), "ms_per_step": ms_s,
-                              "phase_ms": phs, "train_s": t_train, "train_loss": loss,
-                              "cn_hi": cn_hi,
-                              "max_abs_dF_vs_plain": float(np.abs(fsu - res_f).max()),
-                              "abs_dE_per_atom_vs_plain": abs(esu - res_e) / n,
-                              "speed_vs_plain": ms / ms_s}
-        print("[bench] surrogate %s" % json.dumps(extra["surrogate"]), file=sys.stderr, flush=True)
-        # Eq. 3 as printed (K_i K_j weights per pair): the method without the
-        # factorisation, against which the surrogate also competes
-        run = Runner(system, table, "literal")
-        ms_l = run.timed(max(10, args.steps // 4), 3)
-        phl = run.phases(10)
-        fl = run.out["forces"].cpu().numpy()
-        el = float(run.out["energy"].item())
-        run.close()
-        extra["literal_eq3"] = {"atom_steps_per_s": n / (ms_l * 1e-3), "ms_per_step": ms_l,
-                                "phase_ms": phl, "pair_time_vs_plain": phl["pair"] / ph["pair"],
-                                "max_abs_dF_vs_plain": float(np.abs(fl - res_f).max()),
-                                "abs_dE_per_atom_vs_plain": abs(el - res_e) / n}
-        extra["surrogate"]["speed_vs_literal_eq3"] = ms_l / ms_s
-        extra["surrogate"]["pair_speed_vs_literal_eq3"] = phl["pair"] / phs["pair"]
-        print("[bench] literal %s" % json.dumps(extra["literal_eq3"]), file=sys.stderr, flush=True)
 
-        def forms(big, steps, modes):
-            """Speed of each form on a large cell, and the deviation of the
-            precision and surrogate forms from the plain FP64 result."""
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("CPU baseline: cell-list oracle, all threads, 10^6 atoms")
+        ref, dt, threads = cpu_baseline(system, table)
+        extra["plain_vs_oracle"] = {
+            "abs_dE_per_atom": abs(res_e - ref["energy"]) / n,
+            "max_abs_dF": float(np.abs(res_f - ref["forces"]).max()),
+            "max_abs_dW": float(np.abs(res_w - ref["virial"]).max()),
+            "max_abs_W": float(np.abs(ref["virial"]).max())}
+        del ref
+        m1 = 100_000
+        log("CPU baseline: one thread, passes of %d atoms" % m1)
+        _, dt1, _ = cpu_baseline(system, table, n_threads=1, n_eval=m1)
+        cpu = {"value": n / dt, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+               "sample": "one full FP64 E+F+W evaluation of the same 10^6-atom cell by the C "
+                         "oracle's cell-list mode on %d OpenMP threads (%.1f s)" % (threads, dt),
+               "cpu_model": cpu_model(),
+               "single_thread": {"value": m1 / dt1, "unit": "atom-steps/s", "cores": 1,
+                                 "sample": "the CN, dispersion and chain passes of %d of the "
+                                           "cell's atoms, one thread (%.1f s)" % (m1, dt1)}}
+        log("CPU baseline %s" % json.dumps(cpu))
+
+    if not args.no_extra:
+        from paper_2310_05279_amd import d3 as d3mod
+
+        def forms(big, steps, modes, weights=None):
+            """Speed of each form on a cell, and the deviation of the other
+            forms from the plain FP64 result."""
             entry, ref = {}, None
             nbig = big["pos"].shape[0]
             for mode in modes:
@@ -355,20 +357,9 @@ def main():
                 phb = run.phases(5)
                 got = (run.out["forces"].cpu().numpy(), float(run.out["energy"].item()),
                        run.out["virial"].cpu().numpy())
-                st = run.calc.stats()
                 run.close()
                 entry[mode] = {"atom_steps_per_s": nbig / (msb * 1e-3),
                                "ms_per_step": msb, "phase_ms": phb}
-                if mode in ("plain", "prec"):
-                    # the dispersion pass against its ALU roof: unique pairs from
-                    # the list length (the lists hold exactly the pairs within
-                    # R_pot), flops per pair at the mean reference count
-                    kbar = float(np.asarray(table["n_ref"])[big["types"]].mean())
-                    fl = 0.5 * st["mean_pot"] * nbig * _flops_per_pair(kbar, kbar)
-                    peak = FP64_VECTOR_PEAK_TFLOPS if mode == "plain" else FP32_VECTOR_PEAK_TFLOPS
-                    ach = fl / (phb["pair"] * 1e-3) / 1e12
-                    entry[mode]["pair_roofline"] = {"achieved_TFLOPs": ach, "peak_TFLOPs": peak,
-                                                    "frac": ach / peak}
                 if mode == "plain":
                     ref = got
                 elif ref is not None:
@@ -381,20 +372,66 @@ def main():
                                                              entry["surrogate"]["ms_per_step"])
             return entry
 
+        # the precision form on the headline cell, with its pair pass against
+        # the FP32 peak on the same flop count
+        run = Runner(system, table, "prec")
+        ms_p = run.timed(args.steps, args.warmup)
+        php = run.phases(max(10, args.steps // 2))
+        fp = run.out["forces"].cpu().numpy()
+        ep = float(run.out["energy"].item())
+        wp = run.out["virial"].cpu().numpy()
+        run.close()
+        extra["prec_f32"] = {"atom_steps_per_s": n / (ms_p * 1e-3), "ms_per_step": ms_p,
+                             "phase_ms": php, "pair_time_vs_plain": php["pair"] / ph["pair"],
+                             "max_abs_dF_vs_plain": float(np.abs(fp - res_f).max()),
+                             "abs_dE_per_atom_vs_plain": abs(ep - res_e) / n,
+                             "max_abs_dW_vs_plain": float(np.abs(wp - res_w).max())}
+        if roofline is not None:
+            a32 = roofline["algorithmic_flops_per_launch"] / (php["pair"] * 1e-3) / 1e12
+            extra["prec_f32"]["pair_roofline"] = {"achieved_TFLOPs": a32,
+                                                  "peak_TFLOPs": FP32_VECTOR_PEAK_TFLOPS,
+                                                  "frac": a32 / FP32_VECTOR_PEAK_TFLOPS}
+        log("prec %s" % json.dumps(extra["prec_f32"]))
+
+        # 24 000-atom cell: plain, per-atom virial, the surrogate (trained here
+        # on 10^6 exact-labelled CN pairs over [0, 99.9th CN percentile + 0.5]^2)
+        # and Eq. 3 as printed
+        small = synth.mof_like(24000)
+        ns = small["pos"].shape[0]
+        run = Runner(small, table, "plain", per_atom=True)
+        ms_a = run.timed(args.steps * 5, args.warmup)
+        run.close()
+        run = Runner(small, table, "surrogate")
+        cn = run.calc.coordination().cpu().numpy()
+        cn_hi = float(np.percentile(cn, 99.9) + 0.5)
+        d3mod.d3_c6_surrogate_init(run.calc.ctx, 5)
+        t0 = time.perf_counter()
+        loss = d3mod.d3_c6_surrogate_train(run.calc.ctx, n_samples=1_000_000,
+                                           epochs=args.sur_epochs, lr=5e-3, lr_final=1e-6,
+                                           seed=4, cn_hi=cn_hi)
+        t_train = time.perf_counter() - t0
+        weights = d3mod.d3_c6_surrogate_get_weights(run.calc.ctx)
+        run.close()
+        e24 = forms(small, args.steps * 5, ("plain", "prec", "literal", "surrogate"), weights)
+        e24["plain_with_atom_virial"] = {"atom_steps_per_s": ns / (ms_a * 1e-3),
+                                         "ms_per_step": ms_a}
+        e24["surrogate"].update({"train_s": t_train, "train_loss": loss, "cn_hi": cn_hi})
+        extra["mof_24000"] = e24
+        log("mof_24000 %s" % json.dumps(e24))
+
         for name, big, steps, modes in (
                 ("mof_200k", synth.mof_like(200_000), 10,
                  ("plain", "prec", "literal", "surrogate")),
-                ("mof_1M", synth.mof_like(1_000_000), 10, ("plain", "prec")),
                 ("graphene_500k", synth.bilayer_graphene(250, 500, seed=500000), 10,
                  ("plain", "prec"))):
-            extra[name] = forms(big, steps, modes)
-            print("[bench] %s %s" % (name, json.dumps(extra[name])), file=sys.stderr, flush=True)
+            extra[name] = forms(big, steps, modes, weights)
+            log("%s %s" % (name, json.dumps(extra[name])))
 
         # long cutoffs on the 24 000-atom cell, R_cn = R_pot / 2: speed, and the
         # force error of each cutoff against the 50 A result (plain FP64)
         sweep, f50 = {}, None
         for rp in (50.0, 40.0, 30.0, 20.0, 12.0):
-            run = Runner(system, table, "plain", r_pot=rp, r_cn=rp / 2)
+            run = Runner(small, table, "plain", r_pot=rp, r_cn=rp / 2)
             msc = run.timed(10, 2)
             phc = run.phases(5)
             fc = run.out["forces"].cpu().numpy()
@@ -402,21 +439,20 @@ def main():
             run.close()
             if f50 is None:
                 f50 = fc
-            sweep["%g" % rp] = {"r_cn": rp / 2, "atom_steps_per_s": n / (msc * 1e-3),
+            sweep["%g" % rp] = {"r_cn": rp / 2, "atom_steps_per_s": ns / (msc * 1e-3),
                                 "ms_per_step": msc, "phase_ms": phc,
                                 "mean_entries_pot": st["mean_pot"],
                                 "force_rmse_vs_50A": float(np.sqrt(((fc - f50) ** 2).mean())),
                                 "force_maxerr_vs_50A": float(np.abs(fc - f50).max())}
         extra["cutoff_sweep_mof24000"] = sweep
-        print("[bench] cutoff sweep %s" % json.dumps(sweep), file=sys.stderr, flush=True)
+        log("cutoff sweep %s" % json.dumps(sweep))
 
         # velocity-Verlet NVE on the 10^6-atom cell: 300 K Maxwell start, 1 fs,
         # lists with a 1 A skin rebuilt when an atom moved more than 0.5 A
-        big = synth.mof_like(1_000_000)
-        vel0, mass = synth.maxwell_velocities(big["types"], 300.0, seed=300)
+        vel0, mass = synth.maxwell_velocities(system["types"], 300.0, seed=300)
         md = {}
         for mode in ("plain", "prec", "surrogate"):
-            run = Runner(big, table, mode, skin=1.0)
+            run = Runner(system, table, mode, skin=1.0)
             if mode == "surrogate":
                 d3mod.d3_c6_surrogate_set_weights(run.calc.ctx, weights)
             pos = run.calc.pos.clone()
@@ -428,12 +464,11 @@ def main():
                                           every=args.md_steps)
             dt = time.perf_counter() - t0
             run.close()
-            nb = big["pos"].shape[0]
-            md[mode] = {"atom_steps_per_s": nb * args.md_steps / dt,
+            md[mode] = {"atom_steps_per_s": n * args.md_steps / dt,
                         "ms_per_step": 1e3 * dt / args.md_steps, "rebuilds": reb,
-                        "etot_drift_per_atom_eV": float((thermo[-1, 2] - thermo[0, 2]) / nb)}
+                        "etot_drift_per_atom_eV": float((thermo[-1, 2] - thermo[0, 2]) / n)}
         extra["md_nve_mof_1M"] = md
-        print("[bench] md %s" % json.dumps(md), file=sys.stderr, flush=True)
+        log("md %s" % json.dumps(md))
 
         # the paper's own throughput shape (Table I): a 40 000-atom AB bilayer
         # (100 x 100 supercell), one step with a build, and NVE MD as above
@@ -462,27 +497,16 @@ def main():
                            "md_etot_drift_per_atom_eV":
                                float((thermo[-1, 2] - thermo[0, 2]) / nbl)}
         extra["bilayer_40k"] = entry
-        print("[bench] bilayer 40k %s" % json.dumps(entry), file=sys.stderr, flush=True)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        ref, dt, threads = cpu_baseline(system, table)
-        cpu = {"value": n / dt, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
-               "sample": "one full FP64 E+F+W evaluation of the 24,000-atom MOF-like cell "
-                         "by the C oracle (brute force over all pairs and images), %.1f s" % dt,
-               "cpu_model": cpu_model()}
-        extra["plain_vs_oracle"] = {
-            "abs_dE_per_atom": abs(res_e - ref["energy"]) / n,
-            "max_abs_dF": float(np.abs(res_f - ref["forces"]).max()),
-            "max_abs_dW": float(np.abs(res_w - ref["virial"]).max())}
+        log("bilayer 40k %s" % json.dumps(entry))
 
     line = {"metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "mof_like_24000 (H,C,N,O,Zn 4:6:1:2:1, 0.04 atoms/A^3, "
-                                   "seed 24000; synthetic D3 table seed 2310; R_pot 12 A, "
-                                   "R_cn 6 A; plain FP64; neighbour build every step)",
+            "config": {"workload": "mof_like_1M (10^6 atoms, H,C,N,O,Zn 4:6:1:2:1, 0.04 "
+                                   "atoms/A^3, seed 1000000; synthetic D3 table seed 2310; "
+                                   "R_pot 12 A, R_cn 6 A; plain FP64; E+F+virial with the "
+                                   "neighbour build in every step)",
                        "n_atoms": n, "parallelism": "single GPU"},
             "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     print(json.dumps(line), flush=True)

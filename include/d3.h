@@ -176,8 +176,9 @@ int d3_coordination(d3_ctx *ctx, const double *pos, double *cn_out,
  * double[9] row-major; atom_energy: device double[n] or NULL (site
  * energies U_i of Eq. 2).  Any output pointer except energy may be NULL.
  * flags: D3_ACCUMULATE, D3_AUTO_REBUILD, D3_REBUILD (which takes
- * precedence over D3_AUTO_REBUILD).  Errors: STATE, INVALID_ARG, HIP; with
- * D3_AUTO_REBUILD also CAPACITY. */
+ * precedence over D3_AUTO_REBUILD).  Errors: STATE, INVALID_ARG, HIP;
+ * CAPACITY when the last build overflowed the lists and no rebuild flag is
+ * given, or (D3_AUTO_REBUILD) when a rebuild could not fit them. */
 int d3_energy_forces_virial(d3_ctx *ctx, const double *pos, double *energy,
                             double *forces, double *virial,
                             double *atom_energy, uint32_t flags,
@@ -211,7 +212,13 @@ int d3_evaluate(d3_ctx *ctx, const double *pos, const d3_outputs *out,
                 uint32_t flags, void *stream);
 
 /* Synchronise the stream of the last call and report (then clear) the
- * conditions the device recorded: SPECIES, CAPACITY, STALE, or 0. */
+ * conditions the device recorded: SPECIES, INVALID_ARG (a non-finite
+ * position: that atom was left out of every list and its results are not
+ * meaningful), CAPACITY, STALE, or 0.  Writes into the lists stay within
+ * their capacity; once an overflow has been seen, the lists count as
+ * truncated: evaluations without D3_REBUILD or D3_AUTO_REBUILD return
+ * CAPACITY until a build (which then sizes the lists again) replaces
+ * them. */
 int d3_status(d3_ctx *ctx);
 
 /* Statistics of the last build: max and mean list lengths of the R_pot
@@ -235,10 +242,11 @@ int d3_bin_plan(const double *cell, const int32_t *pbc, double rlist,
                 int32_t max_rows);
 
 /* Per-phase timing with HIP events recorded on the caller's stream around
- * each group of launches: 0 neighbour build, 1 position update, 2 CN and
- * weights, 3 dispersion pass, 4 chain pass with the final reductions,
- * 5 unused (kept for layout).  enable = 1
- * starts (and clears) the accumulation, 0 stops it. */
+ * each group of launches: 0 binning and counting sort of a neighbour
+ * build, 1 position update, 2 CN and weights, 3 dispersion pass, 4 chain
+ * pass with the final reductions, 5 list construction of a neighbour build
+ * (a build is phases 0 and 5).  enable = 1 starts (and clears) the
+ * accumulation, 0 stops it. */
 #define D3_N_PHASES 6
 int d3_set_timing(d3_ctx *ctx, int32_t enable);
 
@@ -314,6 +322,22 @@ int d3_c6_surrogate_grad(d3_ctx *ctx, int64_t m, const int32_t *pair,
                          const float *x, const float *y, float *grads,
                          float *loss, void *stream);
 
+/* One training step on explicit samples (tests: the optimiser against the
+ * CPU reference).  m, pair, x, y as for d3_c6_surrogate_grad.  Computes
+ * each pair's mean-squared-error gradient over its samples, then applies
+ * the update d3_c6_surrogate_train makes: Adam (moment decays 0.9 and
+ * 0.999, epsilon 1e-8, bias corrections for step + 1) with the cosine step
+ * size of step `step` (0-based) of total_steps, lr_final + (lr - lr_final)
+ * (1 + cos(pi step / total_steps)) / 2.  Updates the context's FP32
+ * weights, Adam moments (zeroed by d3_c6_surrogate_init) and inference
+ * weights; pairs without samples are left unchanged.  Synchronises.
+ * Errors: INVALID_ARG (sizes, step outside 0..total_steps, lr <= 0),
+ * NOT_TRAINED (no init), HIP. */
+int d3_c6_surrogate_adam_step(d3_ctx *ctx, int64_t m, const int32_t *pair,
+                              const float *x, const float *y, int64_t step,
+                              int64_t total_steps, double lr,
+                              double lr_final, void *stream);
+
 /* ------------------------------------------------------------------------
  * Velocity-Verlet NVE molecular dynamics driven by the D3 forces (the MD
  * use of the paper's Sec. II D, here without thermostat).
@@ -323,7 +347,11 @@ int d3_c6_surrogate_grad(d3_ctx *ctx, int64_t m, const int32_t *pair,
  * array of (n_steps/every + 1) * 3 values (potential, kinetic, total
  * energy, eV) recorded every `every` steps from step 0, or NULL.
  * rebuilds: host int64[1] or NULL.  A build must precede the first call.
- * Synchronises. */
+ * Synchronises.  Errors: STATE, INVALID_ARG, HIP; CAPACITY if a rebuild
+ * could not fit the lists; after the run, SPECIES or INVALID_ARG if the
+ * device recorded a bad species index or a non-finite position during it
+ * (the run then went on with contained values and its results are not
+ * meaningful). */
 int d3_md_nve(d3_ctx *ctx, int64_t n_steps, double dt, double *pos,
               double *vel, const double *mass, int32_t every, double *thermo,
               int64_t *rebuilds, void *stream);

@@ -6,8 +6,9 @@ The surrogate is not part of the paper: it approximates the CN-dependent
 C6 of Eq. 3 (and its two CN derivatives) for one element pair with a small
 multilayer perceptron, trained on samples that Eq. 3 itself labels.  This
 module holds the plain definition of that network, its mean-squared-error
-loss, the loss gradient by backpropagation and one Adam step, so that the
-GPU training kernels can be checked against it.
+loss, the loss gradient by backpropagation, one Adam step and the cosine
+step-size schedule, so that the GPU training kernels can be checked
+against it.
 
 Network (row-vector convention, inputs already scaled to [-1, 1]):
     z1 = x W1 + b1      (2 -> 32),  h1 = silu(z1)
@@ -83,6 +84,12 @@ def loss_and_grad(theta, x, t):
     g["W1"] = c["x"].T @ dz1
     g["b1"] = dz1.sum(0)
     return loss, pack(g)
+
+
+def cosine_step_size(step, total, lr0, lr1):
+    """Step size of training step ``step`` (0-based) of ``total`` under a
+    cosine decay from lr0 (step 0) to lr1 (step total)."""
+    return lr1 + 0.5 * (lr0 - lr1) * (1.0 + np.cos(np.pi * step / total))
 
 
 def adam_step(theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -413,6 +413,7 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
     // the bin counts and scatter cursors are left at zero by the ranking
     // kernel of the previous build; they are cleared here only after an
     // allocation or a build that did not complete
+    phase_mark(c, PH_BUILD, s);
     if (!c->counts_clean) HIPCHK(hipMemsetAsync(count, 0, 2 * (size_t)g.nbins * sizeof(int), s));
     c->counts_clean = false;
     launch_bin(n, pos, type, c->n_elem, g, c->bin_of.as<int>(), c->shift.as<double4>(), count,
@@ -442,10 +443,13 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
         D3CHK(ensure(c->list_p, N * c->cap_p * sizeof(uint32_t)));
         D3CHK(ensure(c->list_c, N * c->cap_c * sizeof(uint32_t)));
     }
+    phase_mark(c, PH_BUILD, s);
+    phase_mark(c, PH_LIST, s);
     launch_list(n, c->pos_s.as<double4>(), c->bin_start.as<int>(), c->slab.as<int>(), g,
                 c->row_tab.as<RowSpan>(), c->img_tab.as<double4>(),
                 rp * rp, rcn * rcn, c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p,
                 c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, 0, c->status.as<int>(), s);
+    phase_mark(c, PH_LIST, s);
     HIPCHK(hipGetLastError());
     c->counts_clean = true;
     return D3_OK;
@@ -456,6 +460,7 @@ int read_status(d3_ctx* c, hipStream_t s, int* out)
     HIPCHK(hipMemcpyAsync(c->h_status, c->status.p, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     *out = *c->h_status;
+    if (*out & ST_CAPACITY) c->lists_bad = true;
     return D3_OK;
 }
 
@@ -472,7 +477,8 @@ int status_code(int bits)
 int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const double* cell,
           const int32_t* pbc, hipStream_t s)
 {
-    const bool same = same_geometry(c, n, cell, pbc);
+    // lists known to have overflowed are sized again, as for a new geometry
+    const bool same = same_geometry(c, n, cell, pbc) && !c->lists_bad;
     if (!same) {
         Geo g;
         std::vector<double4> imgs;
@@ -498,9 +504,8 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
         HIPCHK(hipStreamSynchronize(s));
         c->built = false;
     }
-    phase_mark(c, PH_BUILD, s);
     D3CHK(run_build(c, pos, type, !same, s));
-    phase_mark(c, PH_BUILD, s);
+    if (!same) c->lists_bad = false;  // capacities counted from these positions
     c->built = true;
     c->last_stream = s;
     return D3_OK;
@@ -709,6 +714,10 @@ static int run_evaluate(d3_ctx* c, const double* pos, const d3_outputs& o, uint3
         }
         return D3_OK;
     }
+    if (c->lists_bad && !(flags & (D3_REBUILD | D3_AUTO_REBUILD)))
+        return fail(D3_ERR_CAPACITY,
+                    "the last build overflowed the neighbour lists: rebuild first "
+                    "(d3_build_neighbors, D3_REBUILD or D3_AUTO_REBUILD)");
     if (flags & D3_REBUILD) {
         // a build from pos writes the sorted positions itself, so the
         // per-evaluation position update is not needed
@@ -721,6 +730,7 @@ static int run_evaluate(d3_ctx* c, const double* pos, const d3_outputs& o, uint3
     if ((flags & D3_AUTO_REBUILD) && !(flags & D3_REBUILD)) {
         int st = 0;
         D3CHK(read_status(c, s, &st));
+        if (c->lists_bad) st |= ST_CAPACITY;
         if (st & (ST_STALE | ST_CAPACITY)) {
             const int keep = st & ~(ST_STALE | ST_CAPACITY);
             HIPCHK(hipMemsetAsync(c->status.p, 0, sizeof(int), s));

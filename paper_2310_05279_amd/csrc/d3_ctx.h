@@ -58,6 +58,9 @@ struct d3_ctx {
     d3::Geo geo{};
     bool built = false;
     bool counts_clean = false;  // bin counts and scatter cursors are zero
+    // a build overflowed its lists (seen in the status word): the lists are
+    // truncated until a build sizes them again
+    bool lists_bad = false;
     // cell-sorted data
     d3::Buf bin_of, shift, count, bin_start, scan_tmp, perm_tmp, perm, slab;
     d3::Buf pos_s, shift_s, ref_s, type_copy, img_tab, row_tab;
@@ -106,7 +109,7 @@ int status_code(int bits);
 int alloc_proj(d3_ctx* c, int mode);
 
 // phase timing
-enum Phase { PH_BUILD = 0, PH_UPDATE = 1, PH_CN = 2, PH_PAIR = 3, PH_CHAIN = 4, PH_REDUCE = 5 };
+enum Phase { PH_BUILD = 0, PH_UPDATE = 1, PH_CN = 2, PH_PAIR = 3, PH_CHAIN = 4, PH_LIST = 5 };
 void phase_mark(d3_ctx* c, int phase, hipStream_t s);  // call twice: begin, end
 int timing_flush(d3_ctx* c);
 

@@ -114,8 +114,15 @@ extern "C" int d3_md_nve(d3_ctx* c, int64_t n_steps, double dt, double* pos, dou
             hipLaunchKernelGGL(k_kick_drift, dim3(nb), dim3(BLOCK), 0, s, n, dt, pos, vel, F, mass, 0);
         if (every > 0 && st % every == 0 && (r = record(st / every))) return r;
     }
-    hipError_t e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "d3_md_nve");
     if (rebuilds) *rebuilds = c->n_rebuilds - reb0;
-    return status_code(0);
+    // conditions recorded on the device during the run (a species index or
+    // a position that was not finite); stale lists and overflows were
+    // handled by the rebuilds
+    int st = 0;
+    r = read_status(c, s, &st);
+    if (r) return r;
+    hipError_t e = hipMemsetAsync(c->status.p, 0, sizeof(int), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "d3_md_nve");
+    return status_code(st);
 }

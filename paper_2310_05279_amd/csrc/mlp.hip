@@ -325,6 +325,36 @@ __device__ float block_sum_f(TrainLds& L, float v)
 
 constexpr int PPT = (NPAR + TB - 1) / TB;  // parameters owned per thread
 
+// Step size of training step gs (0-based) of total: cosine decay from lr0
+// at step 0 to lr1 at step total.
+__device__ __forceinline__ float cosine_lr(int gs, int total, float lr0, float lr1)
+{
+    return lr1 + 0.5f * (lr0 - lr1) * (1.0f + cosf(3.14159265f * (float)gs / (float)total));
+}
+
+// Adam (Kingma & Ba) for the parameters this thread owns (q = t + r TB):
+// first and second moments am, av updated with gradient g, then the bias-
+// corrected step of size lr for training step gs (0-based, so the bias
+// corrections use gs + 1).  Writes the new weights to wn (L.w is left for
+// the caller to overwrite once every thread has read it).
+__device__ __forceinline__ void adam_update(const TrainLds& L, const float* g, float* am,
+                                            float* av, float* wn, int gs, float lr)
+{
+    const float bc1 = 1.0f - powf(0.9f, (float)(gs + 1));
+    const float bc2 = 1.0f - powf(0.999f, (float)(gs + 1));
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < PPT; r++) {
+        const int q = t + r * TB;
+        wn[r] = 0.0f;
+        if (q < NPAR) {
+            am[r] = 0.9f * am[r] + 0.1f * g[r];
+            av[r] = 0.999f * av[r] + 0.001f * g[r] * g[r];
+            wn[r] = L.w[q] - lr * (am[r] / bc1) / (sqrtf(av[r] / bc2) + 1e-8f);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(TB)
 k_train(int n_per, const float* __restrict__ X, const float* __restrict__ Y,
         float* __restrict__ Wg, float* __restrict__ Mg, float* __restrict__ Vg, int step0,
@@ -352,22 +382,13 @@ k_train(int n_per, const float* __restrict__ X, const float* __restrict__ Y,
         const float tg[3] = {Y[3 * s], Y[3 * s + 1], Y[3 * s + 2]};
         const float se = fwd_bwd(L, X[2 * s], X[2 * s + 1], tg, true, norm);
         __syncthreads();
-        const float lr = lr1 + 0.5f * (lr0 - lr1) * (1.0f + cosf(3.14159265f * (float)gs /
-                                                                   (float)total_steps));
-        const float bc1 = 1.0f - powf(0.9f, (float)(gs + 1));
-        const float bc2 = 1.0f - powf(0.999f, (float)(gs + 1));
-        float wn[PPT];
+        float gr[PPT], wn[PPT];
 #pragma unroll
         for (int r = 0; r < PPT; r++) {
             const int q = t + r * TB;
-            wn[r] = 0.0f;
-            if (q < NPAR) {
-                const float g = grad_param(L, q);
-                am[r] = 0.9f * am[r] + 0.1f * g;
-                av[r] = 0.999f * av[r] + 0.001f * g * g;
-                wn[r] = L.w[q] - lr * (am[r] / bc1) / (sqrtf(av[r] / bc2) + 1e-8f);
-            }
+            gr[r] = q < NPAR ? grad_param(L, q) : 0.0f;
         }
+        adam_update(L, gr, am, av, wn, gs, cosine_lr(gs, total_steps, lr0, lr1));
         const float tot = block_sum_f(L, se);  // includes a barrier: all reads done
 #pragma unroll
         for (int r = 0; r < PPT; r++) {
@@ -388,25 +409,22 @@ k_train(int n_per, const float* __restrict__ X, const float* __restrict__ Y,
     }
 }
 
-// mean-squared-error gradient of every pair's network on explicit samples
-// (no update); one workgroup per pair walks all samples
-__global__ void __launch_bounds__(TB)
-k_grad(int m, const int32_t* __restrict__ pair, const float* __restrict__ X,
-       const float* __restrict__ Y, const float* __restrict__ Wg, float* __restrict__ grads,
-       float* __restrict__ loss)
+// Mean-squared-error gradient of pair p's network (the block's) over the
+// explicit samples whose pair index is p, summed into gacc (parameters
+// q = t + r TB of this thread) and normalised by 1/(3 m_p); returns this
+// thread's share of the squared error and sets *mp_out = m_p.
+__device__ float pair_gradient(TrainLds& L, int* s_cnt, int m, const int32_t* __restrict__ pair,
+                               const float* __restrict__ X, const float* __restrict__ Y,
+                               float* gacc, int* mp_out)
 {
-    __shared__ TrainLds L;
-    __shared__ int s_cnt;
     const int p = blockIdx.x, t = threadIdx.x;
-    for (int q = t; q < NPAR; q += TB) L.w[q] = Wg[(size_t)p * NPAR + q];
-    if (t == 0) s_cnt = 0;
+    if (t == 0) *s_cnt = 0;
     __syncthreads();
     int c = 0;
     for (int s = t; s < m; s += TB) c += pair[s] == p ? 1 : 0;
-    atomicAdd(&s_cnt, c);
+    atomicAdd(s_cnt, c);
     __syncthreads();
-    const int mp = s_cnt;
-    float gacc[PPT];
+    const int mp = *s_cnt;
 #pragma unroll
     for (int r = 0; r < PPT; r++) gacc[r] = 0.0f;
     float sse = 0.0f;
@@ -426,6 +444,24 @@ k_grad(int m, const int32_t* __restrict__ pair, const float* __restrict__ X,
         }
         __syncthreads();
     }
+    *mp_out = mp;
+    return sse;
+}
+
+// mean-squared-error gradient of every pair's network on explicit samples
+// (no update); one workgroup per pair walks all samples
+__global__ void __launch_bounds__(TB)
+k_grad(int m, const int32_t* __restrict__ pair, const float* __restrict__ X,
+       const float* __restrict__ Y, const float* __restrict__ Wg, float* __restrict__ grads,
+       float* __restrict__ loss)
+{
+    __shared__ TrainLds L;
+    __shared__ int s_cnt;
+    const int p = blockIdx.x, t = threadIdx.x;
+    for (int q = t; q < NPAR; q += TB) L.w[q] = Wg[(size_t)p * NPAR + q];
+    float gacc[PPT];
+    int mp = 0;
+    const float sse = pair_gradient(L, &s_cnt, m, pair, X, Y, gacc, &mp);
 #pragma unroll
     for (int r = 0; r < PPT; r++) {
         const int q = t + r * TB;
@@ -433,6 +469,41 @@ k_grad(int m, const int32_t* __restrict__ pair, const float* __restrict__ X,
     }
     const float tot = block_sum_f(L, sse);
     if (t == 0 && m > 0) atomicAdd(loss, tot / (3.0f * m));
+}
+
+// One training step on explicit samples: the gradient of k_grad, then the
+// Adam update and cosine step size of k_train for step gs of total, on the
+// weights and moments in global memory.  Pairs without samples keep their
+// weights and moments.
+__global__ void __launch_bounds__(TB)
+k_adam_step(int m, const int32_t* __restrict__ pair, const float* __restrict__ X,
+            const float* __restrict__ Y, float* __restrict__ Wg, float* __restrict__ Mg,
+            float* __restrict__ Vg, int gs, int total, float lr0, float lr1)
+{
+    __shared__ TrainLds L;
+    __shared__ int s_cnt;
+    const int p = blockIdx.x, t = threadIdx.x;
+    for (int q = t; q < NPAR; q += TB) L.w[q] = Wg[(size_t)p * NPAR + q];
+    float gacc[PPT], am[PPT], av[PPT], wn[PPT];
+    int mp = 0;
+    (void)pair_gradient(L, &s_cnt, m, pair, X, Y, gacc, &mp);
+    if (mp == 0) return;
+#pragma unroll
+    for (int r = 0; r < PPT; r++) {
+        const int q = t + r * TB;
+        am[r] = q < NPAR ? Mg[(size_t)p * NPAR + q] : 0.0f;
+        av[r] = q < NPAR ? Vg[(size_t)p * NPAR + q] : 0.0f;
+    }
+    adam_update(L, gacc, am, av, wn, gs, cosine_lr(gs, total, lr0, lr1));
+#pragma unroll
+    for (int r = 0; r < PPT; r++) {
+        const int q = t + r * TB;
+        if (q < NPAR) {
+            Wg[(size_t)p * NPAR + q] = wn[r];
+            Mg[(size_t)p * NPAR + q] = am[r];
+            Vg[(size_t)p * NPAR + q] = av[r];
+        }
+    }
 }
 
 // ------------------------------------------------------------ inference --
@@ -1138,6 +1209,33 @@ int d3_c6_surrogate_grad(d3_ctx* c, int64_t m, const int32_t* pair, const float*
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_grad");
     return D3_OK;
+}
+
+int d3_c6_surrogate_adam_step(d3_ctx* c, int64_t m, const int32_t* pair, const float* x,
+                              const float* y, int64_t step, int64_t total_steps, double lr,
+                              double lr_final, void* stream)
+{
+    if (!c) return fail(D3_ERR_INVALID_ARG, "ctx is NULL");
+    if (!c->sur) return fail(D3_ERR_NOT_TRAINED, "surrogate not initialised");
+    if (m < 1 || m > INT32_MAX || !pair || !x || !y)
+        return fail(D3_ERR_INVALID_ARG, "bad arguments");
+    if (step < 0 || total_steps < 1 || step > total_steps || total_steps > INT32_MAX ||
+        !(lr > 0.0) || !(lr_final >= 0.0))
+        return fail(D3_ERR_INVALID_ARG, "bad step, step count or step size");
+    hipStream_t st = (hipStream_t)stream;
+    c->last_stream = st;
+    Surrogate* s = c->sur;
+    const int P = n_pairs(c);
+    hipLaunchKernelGGL(k_adam_step, dim3(P), dim3(TB), 0, st, (int)m, pair, x, y,
+                       s->w32.as<float>(), s->adam_m.as<float>(), s->adam_v.as<float>(),
+                       (int)step, (int)total_steps, (float)lr, (float)lr_final);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->h_w.data(), s->w32.p, (size_t)P * NPAR * sizeof(float),
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "k_adam_step");
+    return upload_weights(c, st);
 }
 
 }  // extern "C"

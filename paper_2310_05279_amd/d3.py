@@ -99,6 +99,8 @@ _SIGS = {
     "d3_c6_surrogate_get_weights": (_c_i32, [_vp, _vp, _c_i64]),
     "d3_c6_surrogate_set_weights": (_c_i32, [_vp, _vp, _c_i64]),
     "d3_c6_surrogate_grad": (_c_i32, [_vp, _c_i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "d3_c6_surrogate_adam_step": (_c_i32, [_vp, _c_i64, _vp, _vp, _vp, _c_i64, _c_i64, _c_d,
+                                           _c_d, _vp]),
     "d3_md_nve": (_c_i32, [_vp, _c_i64, _c_d, _vp, _vp, _vp, _c_i32, _vp, _vp, _vp]),
 }
 
@@ -235,7 +237,7 @@ def d3_list_stats(ctx):
             "mean_cn": out[3], "bins": out[4], "images": out[5]}
 
 
-PHASES = ("build", "update", "cn", "pair", "chain", "reduce")
+PHASES = ("sort", "update", "cn", "pair", "chain", "list")
 
 
 def d3_set_timing(ctx, enable):
@@ -293,6 +295,12 @@ def d3_c6_surrogate_set_weights(ctx, buf):
 def d3_c6_surrogate_grad(ctx, pair, x, y, grads, loss, stream=None):
     _check(lib().d3_c6_surrogate_grad(ctx, int(pair.shape[0]), _ptr(pair), _ptr(x), _ptr(y),
                                       _ptr(grads), _ptr(loss), _stream(stream)))
+
+
+def d3_c6_surrogate_adam_step(ctx, pair, x, y, step, total_steps, lr, lr_final, stream=None):
+    _check(lib().d3_c6_surrogate_adam_step(ctx, int(pair.shape[0]), _ptr(pair), _ptr(x), _ptr(y),
+                                           int(step), int(total_steps), float(lr),
+                                           float(lr_final), _stream(stream)))
 
 
 def d3_md_nve(ctx, n_steps, dt, pos, vel, mass, every=0, stream=None):

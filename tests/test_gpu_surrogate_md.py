@@ -148,6 +148,54 @@ def test_training_gradient_matches_oracle():
     calc.close()
 
 
+def test_adam_steps_match_oracle():
+    """The GPU optimiser: two training steps on explicit samples (the
+    update and cosine step size the training kernel applies) against the
+    FP64 reference's adam_step and cosine_step_size, fed the gradient the
+    GPU reports for the same weights and samples (the gradient itself is
+    pinned to the FP64 backpropagation by the test above), from the same
+    initial weights and zero moments.  The step-1 update is +-lr for every
+    parameter and step 2 mixes two gradients, so a wrong bias correction,
+    moment decay or step size shows at once."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    calc = d3.D3(TAB)
+    d3.d3_c6_surrogate_init(calc.ctx, 13)
+    w = d3.d3_c6_surrogate_get_weights(calc.ctx)
+    rng = np.random.default_rng(8)
+    total, lr0, lr1 = 10, 2e-3, 1e-5
+    theta = [w[p * M.N_PARAMS:(p + 1) * M.N_PARAMS].astype(np.float64) for p in range(NP)]
+    mom = [(np.zeros(M.N_PARAMS), np.zeros(M.N_PARAMS)) for _ in range(NP)]
+    for step in range(2):
+        m = 900
+        pair = torch.as_tensor(rng.integers(0, NP, m).astype(np.int32), device="cuda")
+        x = torch.as_tensor(rng.uniform(-1, 1, (m, 2)).astype(np.float32), device="cuda")
+        y = torch.as_tensor(rng.normal(size=(m, 3)).astype(np.float32), device="cuda")
+        g = torch.zeros((NP, M.N_PARAMS), dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        d3.d3_c6_surrogate_grad(calc.ctx, pair, x, y, g, loss)
+        d3.d3_c6_surrogate_adam_step(calc.ctx, pair, x, y, step, total, lr0, lr1)
+        torch.cuda.synchronize()
+        g = g.cpu().numpy().astype(np.float64)
+        got = d3.d3_c6_surrogate_get_weights(calc.ctx)
+        lr = M.cosine_step_size(step, total, lr0, lr1)
+        worst = 0.0
+        for p in range(NP):
+            want, mm, vv = M.adam_step(theta[p], g[p], mom[p][0], mom[p][1], step + 1, lr)
+            gp = got[p * M.N_PARAMS:(p + 1) * M.N_PARAMS].astype(np.float64)
+            err = np.abs(gp - want) / (1e-5 * lr + 2e-7 * np.abs(want))
+            worst = max(worst, float(err.max()))
+            # every parameter moved by about lr on the first step
+            if step == 0:
+                assert np.abs(np.abs(gp - theta[p]) - lr).max() < 1e-3 * lr
+            theta[p] = gp
+            mom[p] = (mm, vv)
+        print("adam step %d (lr %.3e): worst error / tolerance %.3f" % (step, lr, worst),
+              flush=True)
+        assert worst <= 1.0
+    calc.close()
+
+
 def _cn_hi(system):
     res = R.d3(system["pos"], system["types"], system["cell"], system["pbc"], TAB)
     return float(np.percentile(res["cn"], 99.9) + 0.5), res
@@ -189,9 +237,17 @@ def test_training_gain(trained):
     assert ea[0] < 1.5e-2
 
 
+SUR_GATE = 1e-4  # eV/A, force max-abs against the exact FP64 oracle
+
+
+@pytest.mark.xfail(strict=True, reason=(
+    "surrogate force gate (1e-4 eV/A against the exact FP64 oracle) not met: max|dF| "
+    "3.0e-2 eV/A on the 3 000-atom cell and 4.7e-2 eV/A on the 200 000-atom cell as measured"))
 def test_surrogate_forces_against_oracle(trained):
-    """Energy, forces and virial with the surrogate C6 against the FP64
-    oracle on a 3000-atom MOF-like cell (errors reported)."""
+    """Energy, forces and virial with the surrogate C6 against the exact
+    FP64 oracle (Eq. 3 itself, no network): every atom of a 3 000-atom
+    MOF-like cell and sampled atoms of the 200 000-atom cell, held to the
+    1e-4 eV/A force gate.  The errors are printed before the gate."""
     torch = _torch()
     from paper_2310_05279_amd import d3
     m, ref = trained["mof"], trained["ref"]
@@ -205,10 +261,23 @@ def test_surrogate_forces_against_oracle(trained):
     de = abs(out["energy"].item() - ref["energy"]) / n
     df = np.abs(out["forces"].cpu().numpy() - ref["forces"]).max()
     dw = np.abs(out["virial"].cpu().numpy() - ref["virial"]).max()
-    print("surrogate vs oracle: |dE|/atom=%.3e max|dF|=%.3e (max|F|=%.3e) max|dW|=%.3e"
-          % (de, df, np.abs(ref["forces"]).max(), dw), flush=True)
-    assert np.isfinite(df) and df < 0.1 * np.abs(ref["forces"]).max()
     calc.close()
+    big = synth.mof_like(200_000)
+    calc = d3.D3(TAB, mode="surrogate")
+    d3.d3_c6_surrogate_set_weights(calc.ctx, trained["w"])
+    calc.build(big["pos"], big["types"], big["cell"], big["pbc"])
+    outb = calc.compute()
+    torch.cuda.synchronize()
+    calc.status()
+    idx = np.random.default_rng(22).choice(big["pos"].shape[0], 8, replace=False)
+    refb = O.sampled(big["pos"], big["types"], big["cell"], big["pbc"], TAB, idx)
+    dfb = np.abs(outb["forces"].cpu().numpy()[idx] - refb["forces"]).max()
+    calc.close()
+    print("surrogate vs exact oracle: 3 000 atoms |dE|/atom=%.3e max|dF|=%.3e (max|F|=%.3e) "
+          "max|dW|=%.3e; 200 000 atoms, sampled: max|dF|=%.3e"
+          % (de, df, np.abs(ref["forces"]).max(), dw, dfb), flush=True)
+    assert np.isfinite(df) and np.isfinite(dfb)
+    assert df <= SUR_GATE and dfb <= SUR_GATE
 
 
 def _network_c6(w, cn_hi):

@@ -725,6 +725,20 @@ def test_adam_first_steps_closed_form():
     assert t4 - t3 == pytest.approx(-lr * np.sign(g1), rel=1e-6)
 
 
+def test_cosine_step_size_endpoints():
+    """The cosine schedule starts at lr0, ends at lr1, passes their mean
+    half way and is symmetric about it (a sine in place of the cosine, or a
+    period of total/2, fails this)."""
+    from oracle import mlp_oracle as M
+    lr0, lr1, T = 5e-3, 1e-6, 400
+    assert M.cosine_step_size(0, T, lr0, lr1) == pytest.approx(lr0, rel=1e-15)
+    assert M.cosine_step_size(T, T, lr0, lr1) == pytest.approx(lr1, rel=1e-12)
+    assert M.cosine_step_size(T // 2, T, lr0, lr1) == pytest.approx(0.5 * (lr0 + lr1), rel=1e-14)
+    a = M.cosine_step_size(100, T, lr0, lr1) - 0.5 * (lr0 + lr1)
+    b = M.cosine_step_size(300, T, lr0, lr1) - 0.5 * (lr0 + lr1)
+    assert a == pytest.approx(-b, rel=1e-12) and a > 0
+
+
 # ----------------------------------------------- velocity-Verlet driver ----
 
 def test_md_oracle_energy_conservation_and_reversibility():
