@@ -232,10 +232,22 @@ k_rank(int n, const int* __restrict__ perm_tmp, const int* __restrict__ bin_of,
     const double4 sh = shift[v];
     const double x = pos[3 * v] + sh.x, y = pos[3 * v + 1] + sh.y, z = pos[3 * v + 2] + sh.z;
     perm[o] = v;
-    pos_s[o] = make_double4(x, y, z, __hiloint2double(0, type_copy[v]));
+    // an atom whose position is not finite (the binning kernel reported it)
+    // is left out of every list: it gets a finite stand-in position and a
+    // mark in the high word of w, which the list kernel reads, so that no
+    // pass ever sees a non-finite coordinate
+    if (isfinite(x) && isfinite(y) && isfinite(z)) {
+        pos_s[o] = make_double4(x, y, z, __hiloint2double(0, type_copy[v]));
+        ref_s[o] = make_double4(x, y, z, 0.0);
+    } else {
+        pos_s[o] = make_double4(0.0, 0.0, 0.0, __hiloint2double(1, type_copy[v]));
+        ref_s[o] = make_double4(0.0, 0.0, 0.0, 0.0);
+    }
     shift_s[o] = sh;
-    ref_s[o] = make_double4(x, y, z, 0.0);
 }
+
+// atom left out of the lists (non-finite position at the build)
+__device__ __forceinline__ bool dead_atom(const double4& p) { return __double2hiint(p.w) != 0; }
 
 // Per-evaluation copy of the caller's positions into the cell-sorted
 // layout, using the wrap shifts of the last build so that list images
@@ -250,11 +262,18 @@ k_update(int n, const double* __restrict__ pos, const int* __restrict__ perm,
     int i = perm[k];
     double4 sh = shift_s[k];
     double x = pos[3 * i] + sh.x, y = pos[3 * i + 1] + sh.y, z = pos[3 * i + 2] + sh.z;
+    double4 p = pos_s[k];
+    // a non-finite position is reported and not copied: the atom keeps its
+    // last finite position (or its stand-in, if the build left it out)
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+        atomicOr(status, ST_NONFINITE);
+        return;
+    }
+    if (dead_atom(p)) return;
     double4 r = ref_s[k];
     double dx = x - r.x, dy = y - r.y, dz = z - r.z;
     double d2 = dx * dx + dy * dy + dz * dz;
     if (!(d2 <= half_skin2)) atomicOr(status, ST_STALE);
-    double4 p = pos_s[k];
     pos_s[k] = make_double4(x, y, z, p.w);
 }
 
@@ -421,7 +440,7 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
                     bool valid[LIST_AHEAD];
 #pragma unroll
                     for (int u = 0; u < LIST_AHEAD; u++) {
-                        valid[u] = kb + u * WAVE + lane < total;
+                        valid[u] = kb + u * WAVE + lane < total && !dead_atom(pp[u]);
                         const double4 T = image<IMG>(s_img, img_tab, (uint32_t)ii[u]);
                         qx[u] = pp[u].x + T.x;
                         qy[u] = pp[u].y + T.y;
@@ -433,6 +452,7 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
                     for (int t = 0; t < na; t++) {
                         const int a = a0 + t;
                         const double4 pa = pos_s[a];
+                        const bool alive = !dead_atom(pa);  // wave-uniform
                         const uint32_t self = ((uint32_t)a << g.img_bits) | img_self;
                         int np_t = __builtin_amdgcn_readlane(np, t);
                         int nc_t = __builtin_amdgcn_readlane(nc, t);
@@ -443,7 +463,7 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
                             if (u >= nch) break;
                             const double dx = qx[u] - pa.x, dy = qy[u] - pa.y, dz = qz[u] - pa.z;
                             const double r2 = dx * dx + dy * dy + dz * dz;
-                            const bool other = valid[u] & (code[u] != self);
+                            const bool other = alive & valid[u] & (code[u] != self);
                             const bool inp = other & (r2 < rp2w);
                             const bool inc =
                                 (!TABLE || kb + u * WAVE < cn_total) & other & (r2 < rc2w);

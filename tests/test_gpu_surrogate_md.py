@@ -185,9 +185,11 @@ def test_adam_steps_match_oracle():
             gp = got[p * M.N_PARAMS:(p + 1) * M.N_PARAMS].astype(np.float64)
             err = np.abs(gp - want) / (1e-5 * lr + 2e-7 * np.abs(want))
             worst = max(worst, float(err.max()))
-            # every parameter moved by about lr on the first step
+            # the first step moves every parameter with a gradient well above
+            # epsilon by lr
             if step == 0:
-                assert np.abs(np.abs(gp - theta[p]) - lr).max() < 1e-3 * lr
+                big = np.abs(g[p]) > 1e-4
+                assert np.abs(np.abs(gp - theta[p])[big] - lr).max() < 1e-3 * lr
             theta[p] = gp
             mom[p] = (mm, vv)
         print("adam step %d (lr %.3e): worst error / tolerance %.3f" % (step, lr, worst),
