@@ -183,7 +183,10 @@ def test_adam_steps_match_oracle():
         for p in range(NP):
             want, mm, vv = M.adam_step(theta[p], g[p], mom[p][0], mom[p][1], step + 1, lr)
             gp = got[p * M.N_PARAMS:(p + 1) * M.N_PARAMS].astype(np.float64)
-            err = np.abs(gp - want) / (1e-5 * lr + 2e-7 * np.abs(want))
+            # FP32 update: the bias correction 1 - 0.999^t cancels (2e-3 at t = 2),
+            # so its rounding gives up to ~3e-5 relative in the step; plus the
+            # rounding of the weight itself
+            err = np.abs(gp - want) / (5e-5 * lr + 2e-7 * np.abs(want))
             worst = max(worst, float(err.max()))
             # the first step moves every parameter with a gradient well above
             # epsilon by lr
