@@ -255,6 +255,39 @@ int d3_set_timing(d3_ctx *ctx, int32_t enable);
 int d3_get_timing(d3_ctx *ctx, double *ms, int64_t *calls);
 
 /* ------------------------------------------------------------------------
+ * Allocation-free evaluation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  One call does what d3_create, d3_build_neighbors and
+ * d3_energy_forces_virial do together, for one small configuration and
+ * without a context: every device buffer the library needs (converted
+ * table, bins, lists, per-atom intermediates, partial sums, status) is
+ * carved from one static device array of D3_NOALLOC_SCRATCH_BYTES, which
+ * the library holds on each GPU it runs on until the process ends, and the
+ * host side uses the stack only (about 150 KB).  No hipMalloc, hipFree or
+ * other allocating routine is called.
+ *   params, table: as for d3_create (mode PLAIN_F64, PREC_F32 or LITERAL;
+ *     skin is used as in a build);  n <= D3_NOALLOC_MAX_ATOMS;
+ *   pos, type, cell, pbc: as for d3_build_neighbors;
+ *   energy, forces, virial, atom_energy: as for d3_energy_forces_virial
+ *     (only energy is required);  flags: 0 or D3_ACCUMULATE.
+ * The call synchronises the stream and returns the conditions the device
+ * recorded (as d3_status would).  Errors: INVALID_ARG (n beyond the limit,
+ * surrogate mode, bad arguments), CAPACITY (more bins than 65536, more than
+ * 1024 periodic images, or neighbour lists beyond the space left in the
+ * array: about 7 million entries in all), CELL, SPECIES, HIP.  Calls on one
+ * GPU share its array: calls that overlap on one GPU (two threads, or
+ * unordered streams) race. */
+#define D3_NOALLOC_MAX_ATOMS 4096
+#define D3_NOALLOC_SCRATCH_BYTES (32u << 20)
+int d3_energy_forces_virial_noalloc(const d3_params *params,
+                                    const d3_table *table, int64_t n,
+                                    const double *pos, const int32_t *type,
+                                    const double *cell, const int32_t *pbc,
+                                    double *energy, double *forces,
+                                    double *virial, double *atom_energy,
+                                    uint32_t flags, void *stream);
+
+/* ------------------------------------------------------------------------
  * Learned C6 surrogate (per element pair: MLP (n_i, n_j) -> (C6,
  * dC6/dn_i, dC6/dn_j), widths 2 -> 32 -> 32 -> 3, SiLU).  Not part of the
  * paper: an approximation of Eq. 3 trained on samples that the exact

@@ -37,10 +37,17 @@ int hip_fail(hipError_t e, const char* what)
     return fail(D3_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// set while an allocation-free entry point runs on this thread: a buffer
+// that would have to grow is an error instead of an allocation
+thread_local bool g_no_alloc = false;
+
 int ensure_bytes(void** p, size_t* have, size_t need)
 {
     if (need == 0) need = 256;
     if (*p && *have >= need) return D3_OK;
+    if (g_no_alloc)
+        return fail(D3_ERR_CAPACITY,
+                    "static scratch too small: a buffer of %zu bytes needs %zu", *have, need);
     if (*p) {
         hipError_t e = hipFree(*p);
         *p = nullptr;
@@ -135,10 +142,8 @@ static double bin_gap2(const double G[3][3], const int d[3], const int* pbc)
 // pair within rcn first.  Left empty (every row of the full stencil, as
 // computed in the kernel) for shallow stencils and for stencils too large
 // for a table.
-static void make_rows(const double* cell, Geo& g, double rlist, double rcn,
-                      std::vector<RowSpan>& rows)
+static void make_rows(const double* cell, Geo& g, double rlist, double rcn, RowSpan* rows)
 {
-    rows.clear();
     g.nrows = g.ncnrows = 0;
     const int rmax = std::max(g.reach[0], std::max(g.reach[1], g.reach[2]));
     const long n0 = 2L * g.reach[0] + 1, n1 = 2L * g.reach[1] + 1, n2 = 2L * g.reach[2] + 1;
@@ -152,27 +157,29 @@ static void make_rows(const double* cell, Geo& g, double rlist, double rcn,
     // far above the rounding of binning and wrapping
     const double lim = rlist * rlist * (1.0 + 1e-9) + 1e-12;
     const double limc = rcn * rcn * (1.0 + 1e-9) + 1e-12;
-    std::vector<RowSpan> cn_rows, far_rows;
-    for (int d2 = -g.reach[2]; d2 <= g.reach[2]; d2++)
-        for (int d1 = -g.reach[1]; d1 <= g.reach[1]; d1++) {
-            int lo = INT32_MAX, hi = INT32_MIN;
-            bool cn = false;
-            for (int d0 = -g.reach[0]; d0 <= g.reach[0]; d0++) {
-                const int d[3] = {d0, d1, d2};
-                const double q = bin_gap2(G, d, g.pbc);
-                if (q <= lim) {
-                    lo = std::min(lo, d0);
-                    hi = std::max(hi, d0);
+    // two sweeps: the rows that can hold R_cn pairs, then the others
+    int nr = 0, ncn = 0;
+    for (int sweep = 0; sweep < 2; sweep++)
+        for (int d2 = -g.reach[2]; d2 <= g.reach[2]; d2++)
+            for (int d1 = -g.reach[1]; d1 <= g.reach[1]; d1++) {
+                int lo = INT32_MAX, hi = INT32_MIN;
+                bool cn = false;
+                for (int d0 = -g.reach[0]; d0 <= g.reach[0]; d0++) {
+                    const int d[3] = {d0, d1, d2};
+                    const double q = bin_gap2(G, d, g.pbc);
+                    if (q <= lim) {
+                        lo = std::min(lo, d0);
+                        hi = std::max(hi, d0);
+                    }
+                    if (q <= limc) cn = true;
                 }
-                if (q <= limc) cn = true;
+                if (lo > hi || cn != (sweep == 0)) continue;
+                if (rows) rows[nr] = RowSpan{d1, d2, lo, hi};
+                nr++;
+                ncn += cn ? 1 : 0;
             }
-            if (lo > hi) continue;
-            (cn ? cn_rows : far_rows).push_back(RowSpan{d1, d2, lo, hi});
-        }
-    rows = cn_rows;
-    rows.insert(rows.end(), far_rows.begin(), far_rows.end());
-    g.nrows = (int)rows.size();
-    g.ncnrows = (int)cn_rows.size();
+    g.nrows = nr;
+    g.ncnrows = ncn;
 }
 
 // Bin layout for list cutoff rlist: nb_k bins along lattice vector k,
@@ -182,7 +189,7 @@ static void make_rows(const double* cell, Geo& g, double rlist, double rcn,
 // stencil can reach on periodic axes, and the row table of a deep stencil
 // (rcn: the shorter list cutoff).
 int make_geo(const double* cell, const int32_t* pbc, double rlist, double rcn, int64_t n,
-             Geo& g, std::vector<double4>& imgs, std::vector<RowSpan>& rows)
+             Geo& g, double4* imgs, RowSpan* rows)
 {
     double la[3];
     for (int k = 0; k < 3; k++)
@@ -243,18 +250,41 @@ int make_geo(const double* cell, const int32_t* pbc, double rlist, double rcn, i
                     (long long)n, nimg);
     g.n_img = (int)nimg;
     g.img_bits = bits;
-    imgs.resize(nimg);
     int c = 0;
-    for (int t0 = -g.timg[0]; t0 <= g.timg[0]; t0++)
-        for (int t1 = -g.timg[1]; t1 <= g.timg[1]; t1++)
-            for (int t2 = -g.timg[2]; t2 <= g.timg[2]; t2++) {
-                double T[3];
-                for (int m = 0; m < 3; m++)
-                    T[m] = t0 * cell[m] + t1 * cell[3 + m] + t2 * cell[6 + m];
-                imgs[c++] = make_double4(T[0], T[1], T[2], 0.0);
-            }
+    if (imgs)
+        for (int t0 = -g.timg[0]; t0 <= g.timg[0]; t0++)
+            for (int t1 = -g.timg[1]; t1 <= g.timg[1]; t1++)
+                for (int t2 = -g.timg[2]; t2 <= g.timg[2]; t2++) {
+                    double T[3];
+                    for (int m = 0; m < 3; m++)
+                        T[m] = t0 * cell[m] + t1 * cell[3 + m] + t2 * cell[6 + m];
+                    imgs[c++] = make_double4(T[0], T[1], T[2], 0.0);
+                }
     make_rows(cell, g, rlist, rcn, rows);
     return D3_OK;
+}
+
+// make_geo into the context's host staging arrays: sized first, then
+// filled; a context without growable staging (the allocation-free entry
+// point) must already hold enough
+int make_geo_staged(d3_ctx* c, const double* cell, const int32_t* pbc, double rlist, double rcn,
+                    int64_t n, Geo& g)
+{
+    D3CHK(make_geo(cell, pbc, rlist, rcn, n, g, nullptr, nullptr));
+    const size_t ni = (size_t)g.n_img, nr = (size_t)std::max(g.nrows, 1);
+    if (c->stage_fixed) {
+        if (ni > c->h_img_cap || nr > c->h_rows_cap)
+            return fail(D3_ERR_CAPACITY, "%zu images or %zu stencil rows exceed the static limits "
+                        "(%zu, %zu)", ni, nr, c->h_img_cap, c->h_rows_cap);
+    } else {
+        c->img_store.resize(ni);
+        c->rows_store.resize(nr);
+        c->h_img = c->img_store.data();
+        c->h_rows = c->rows_store.data();
+        c->h_img_cap = ni;
+        c->h_rows_cap = nr;
+    }
+    return make_geo(cell, pbc, rlist, rcn, n, g, c->h_img, c->h_rows);
 }
 
 static int device_cus()
@@ -279,20 +309,28 @@ int max_pass_blocks()
 int pass_blocks(const void* kernel, int units, size_t dyn_lds)
 {
     // resident workgroups per CU of each kernel, from the runtime's occupancy
+    // (a fixed table: no heap use, so the allocation-free path may call it)
+    constexpr int CACHE = 128;
     static std::mutex mu;
-    static std::vector<std::pair<const void*, int>> cache;
+    static const void* keys[CACHE];
+    static int vals[CACHE];
+    static int used = 0;
     int per_cu = 0;
     {
         std::lock_guard<std::mutex> lock(mu);
-        for (const auto& kv : cache)
-            if (kv.first == kernel) per_cu = kv.second;
+        for (int k = 0; k < used; k++)
+            if (keys[k] == kernel) per_cu = vals[k];
         if (per_cu == 0) {
             int nb = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, BLOCK, dyn_lds) !=
                     hipSuccess || nb < 1)
                 nb = 1;
             (void)hipGetLastError();
-            cache.emplace_back(kernel, nb);
+            if (used < CACHE) {
+                keys[used] = kernel;
+                vals[used] = nb;
+                used++;
+            }
             per_cu = nb;
         }
     }
@@ -341,17 +379,6 @@ static bool same_geometry(const d3_ctx* c, int64_t n, const double* cell, const 
     return true;
 }
 
-#define HIPCHK(call)                                   \
-    do {                                               \
-        hipError_t e_ = (call);                        \
-        if (e_ != hipSuccess) return hip_fail(e_, #call); \
-    } while (0)
-
-#define D3CHK(call)                 \
-    do {                            \
-        int r_ = (call);            \
-        if (r_ != D3_OK) return r_; \
-    } while (0)
 
 int alloc_atoms(d3_ctx* c, int64_t n)
 {
@@ -481,10 +508,8 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
     const bool same = same_geometry(c, n, cell, pbc) && !c->lists_bad;
     if (!same) {
         Geo g;
-        std::vector<double4> imgs;
-        std::vector<RowSpan> rows;
         const double rlist = std::max(c->prm.r_pot, c->prm.r_cn) + c->prm.skin;
-        D3CHK(make_geo(cell, pbc, rlist, c->prm.r_cn + c->prm.skin, n, g, imgs, rows));
+        D3CHK(make_geo_staged(c, cell, pbc, rlist, c->prm.r_cn + c->prm.skin, n, g));
         c->n = n;
         c->geo = g;
         std::memcpy(c->cell, cell, sizeof(c->cell));
@@ -494,12 +519,12 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
         D3CHK(ensure(c->bin_start, ((size_t)g.nbins + 1) * sizeof(int)));
         D3CHK(ensure(c->slab, 16 * sizeof(int)));
         D3CHK(ensure(c->scan_tmp, ((size_t)g.nbins / 1024 + 4) * sizeof(int)));
-        D3CHK(ensure(c->img_tab, imgs.size() * sizeof(double4)));
-        HIPCHK(hipMemcpyAsync(c->img_tab.p, imgs.data(), imgs.size() * sizeof(double4),
+        D3CHK(ensure(c->img_tab, (size_t)g.n_img * sizeof(double4)));
+        HIPCHK(hipMemcpyAsync(c->img_tab.p, c->h_img, (size_t)g.n_img * sizeof(double4),
                               hipMemcpyHostToDevice, s));
-        D3CHK(ensure(c->row_tab, std::max<size_t>(rows.size(), 1) * sizeof(RowSpan)));
-        if (!rows.empty())
-            HIPCHK(hipMemcpyAsync(c->row_tab.p, rows.data(), rows.size() * sizeof(RowSpan),
+        D3CHK(ensure(c->row_tab, (size_t)std::max(g.nrows, 1) * sizeof(RowSpan)));
+        if (g.nrows > 0)
+            HIPCHK(hipMemcpyAsync(c->row_tab.p, c->h_rows, (size_t)g.nrows * sizeof(RowSpan),
                                   hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
         c->built = false;
@@ -537,18 +562,27 @@ int coordination(d3_ctx* c, int mode, hipStream_t s)
     return D3_OK;
 }
 
-}  // namespace d3
-
-using namespace d3;
-
-extern "C" {
-
-const char* d3_last_error(void) { return g_err.c_str(); }
-
-int d3_create(const d3_params* prm, const d3_table* tab, d3_ctx** out)
+// Validation of d3_build_neighbors' arguments (also used by the
+// allocation-free entry point).
+int check_build_args(int64_t n, const double* pos, const int32_t* type, const double* cell,
+                     const int32_t* pbc)
 {
-    if (!out) return fail(D3_ERR_INVALID_ARG, "out is NULL");
-    *out = nullptr;
+    if (n < 0 || n > (int64_t)INT32_MAX / 2) return fail(D3_ERR_INVALID_ARG, "n=%lld out of range", (long long)n);
+    if (n > 0 && (!pos || !type)) return fail(D3_ERR_INVALID_ARG, "pos or type is NULL");
+    if (!cell || !pbc) return fail(D3_ERR_INVALID_ARG, "cell or pbc is NULL");
+    for (int k = 0; k < 9; k++)
+        if (!std::isfinite(cell[k])) return fail(D3_ERR_CELL, "non-finite cell");
+    for (int k = 0; k < 3; k++)
+        if (pbc[k] != 0 && pbc[k] != 1) return fail(D3_ERR_INVALID_ARG, "pbc[%d]=%d not 0/1", k, pbc[k]);
+    if (((uintptr_t)pos & 7) || ((uintptr_t)type & 3))
+        return fail(D3_ERR_INVALID_ARG, "misaligned pos or type pointer");
+    return D3_OK;
+}
+
+// Validation of d3_create's arguments (also used by the allocation-free
+// entry point).
+int check_params_table(const d3_params* prm, const d3_table* tab)
+{
     if (!prm || !tab) return fail(D3_ERR_INVALID_ARG, "params or table is NULL");
     if (!(prm->r_pot > 0.0) || !(prm->r_cn > 0.0) || !(prm->skin >= 0.0) ||
         !std::isfinite(prm->r_pot) || !std::isfinite(prm->r_cn) || !std::isfinite(prm->skin))
@@ -582,15 +616,20 @@ int d3_create(const d3_params* prm, const d3_table* tab, d3_ctx** out)
                         return fail(D3_ERR_INVALID_ARG,
                                     "c6_ref not symmetric or not finite at (%d,%d,%d,%d)", e, f, a, b);
                 }
-    d3_ctx* c = new d3_ctx();
-    c->prm = *prm;
-    c->n_elem = ne;
-    HIPCHK(hipGetDevice(&c->device));
-    ElemTab et;
+    return D3_OK;
+}
+
+// The table in eV and Angstrom (FP64, on the host): per-element data, the
+// C6 reference grid [MAXELEM][MAXELEM][MAXREF][MAXREF] and per element
+// pair (Rd^6, Rd^8, R0^2, s8 R0^2), Rd = a1 R0 + a2 (Eq. 2).
+void convert_table(const d3_params* prm, const d3_table* tab, ElemTab& et, double* c6,
+                   double4* pc)
+{
+    const int ne = tab->n_elem;
     std::memset(&et, 0, sizeof(et));
     et.n_elem = ne;
-    std::vector<double> c6((size_t)MAXELEM * MAXELEM * MAXREF * MAXREF, 0.0);
-    std::vector<double4> pc((size_t)MAXELEM * MAXELEM, make_double4(0, 0, 0, 0));
+    for (size_t q = 0; q < (size_t)MAXELEM * MAXELEM * MAXREF * MAXREF; q++) c6[q] = 0.0;
+    for (int q = 0; q < MAXELEM * MAXELEM; q++) pc[q] = make_double4(0, 0, 0, 0);
     const double conv = HARTREE_EV * std::pow(BOHR_ANG, 6);
     for (int e = 0; e < ne; e++) {
         et.n_ref[e] = tab->n_ref[e];
@@ -608,6 +647,32 @@ int d3_create(const d3_params* prm, const d3_table* tab, d3_ctx** out)
             pc[e * MAXELEM + f] = make_double4(rd6, rd6 * rd2, r0sq, prm->s8 * r0sq);
         }
     }
+}
+
+}  // namespace d3
+
+using namespace d3;
+
+extern "C" {
+
+const char* d3_last_error(void) { return g_err.c_str(); }
+
+int d3_create(const d3_params* prm, const d3_table* tab, d3_ctx** out)
+{
+    if (!out) return fail(D3_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    D3CHK(check_params_table(prm, tab));
+    const int ne = tab->n_elem;
+    int device = 0;
+    HIPCHK(hipGetDevice(&device));
+    d3_ctx* c = new d3_ctx();
+    c->prm = *prm;
+    c->n_elem = ne;
+    c->device = device;
+    ElemTab et;
+    std::vector<double> c6((size_t)MAXELEM * MAXELEM * MAXREF * MAXREF, 0.0);
+    std::vector<double4> pc((size_t)MAXELEM * MAXELEM, make_double4(0, 0, 0, 0));
+    convert_table(prm, tab, et, c6.data(), pc.data());
     c->h_c6 = c6;
     c->h_tab = et;
     for (int e = 0; e < ne; e++) c->h_r2r4[e] = tab->r2r4[e];
@@ -659,15 +724,7 @@ int d3_build_neighbors(d3_ctx* c, int64_t n, const double* pos, const int32_t* t
                        const double* cell, const int32_t* pbc, void* stream)
 {
     if (!c) return fail(D3_ERR_INVALID_ARG, "ctx is NULL");
-    if (n < 0 || n > (int64_t)INT32_MAX / 2) return fail(D3_ERR_INVALID_ARG, "n=%lld out of range", (long long)n);
-    if (n > 0 && (!pos || !type)) return fail(D3_ERR_INVALID_ARG, "pos or type is NULL");
-    if (!cell || !pbc) return fail(D3_ERR_INVALID_ARG, "cell or pbc is NULL");
-    for (int k = 0; k < 9; k++)
-        if (!std::isfinite(cell[k])) return fail(D3_ERR_CELL, "non-finite cell");
-    for (int k = 0; k < 3; k++)
-        if (pbc[k] != 0 && pbc[k] != 1) return fail(D3_ERR_INVALID_ARG, "pbc[%d]=%d not 0/1", k, pbc[k]);
-    if (((uintptr_t)pos & 7) || ((uintptr_t)type & 3))
-        return fail(D3_ERR_INVALID_ARG, "misaligned pos or type pointer");
+    D3CHK(check_build_args(n, pos, type, cell, pbc));
     hipStream_t s = (hipStream_t)stream;
     return build(c, n, pos, type, cell, pbc, s);
 }
@@ -825,9 +882,9 @@ int d3_bin_plan(const double* cell, const int32_t* pbc, double rlist, double rcn
     if (!(rlist > 0.0) || !(rcn > 0.0) || rcn > rlist || n < 0 || max_rows < 0)
         return fail(D3_ERR_INVALID_ARG, "bad cutoffs, atom count or row capacity");
     Geo g{};
-    std::vector<double4> imgs;
-    std::vector<RowSpan> table;
-    D3CHK(make_geo(cell, pbc, rlist, rcn, n, g, imgs, table));
+    D3CHK(make_geo(cell, pbc, rlist, rcn, n, g, nullptr, nullptr));
+    std::vector<RowSpan> table((size_t)std::max(g.nrows, 1));
+    D3CHK(make_geo(cell, pbc, rlist, rcn, n, g, nullptr, table.data()));
     for (int k = 0; k < 3; k++) {
         nb[k] = g.nb[k];
         reach[k] = g.reach[k];

@@ -7,6 +7,19 @@
 
 #include "d3_internal.h"
 
+// return from the calling function on a failed HIP call or library call
+#define HIPCHK(call)                                      \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+#define D3CHK(call)                 \
+    do {                            \
+        int r_ = (call);            \
+        if (r_ != D3_OK) return r_; \
+    } while (0)
+
 namespace d3 {
 
 constexpr double BIN_DIV = 3.0;     // bins per list cutoff along each axis (at most)
@@ -61,6 +74,15 @@ struct d3_ctx {
     // a build overflowed its lists (seen in the status word): the lists are
     // truncated until a build sizes them again
     bool lists_bad = false;
+    // host staging of the image translations and stencil row table of a
+    // build: growable vectors, or fixed arrays (stage_fixed) given by the
+    // allocation-free entry point
+    std::vector<double4> img_store;
+    std::vector<d3::RowSpan> rows_store;
+    double4* h_img = nullptr;
+    d3::RowSpan* h_rows = nullptr;
+    size_t h_img_cap = 0, h_rows_cap = 0;
+    bool stage_fixed = false;
     // cell-sorted data
     d3::Buf bin_of, shift, count, bin_start, scan_tmp, perm_tmp, perm, slab;
     d3::Buf pos_s, shift_s, ref_s, type_copy, img_tab, row_tab;
@@ -96,6 +118,12 @@ struct d3_ctx {
 
 namespace d3 {
 
+extern thread_local bool g_no_alloc;
+int check_params_table(const d3_params* prm, const d3_table* tab);
+void convert_table(const d3_params* prm, const d3_table* tab, ElemTab& et, double* c6,
+                   double4* pc);
+int check_build_args(int64_t n, const double* pos, const int32_t* type, const double* cell,
+                     const int32_t* pbc);
 int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const double* cell,
           const int32_t* pbc, hipStream_t s);
 int rebuild_grow(d3_ctx* c, const double* pos, hipStream_t s);

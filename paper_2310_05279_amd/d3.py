@@ -102,6 +102,9 @@ _SIGS = {
     "d3_c6_surrogate_adam_step": (_c_i32, [_vp, _c_i64, _vp, _vp, _vp, _c_i64, _c_i64, _c_d,
                                            _c_d, _vp]),
     "d3_md_nve": (_c_i32, [_vp, _c_i64, _c_d, _vp, _vp, _vp, _c_i32, _vp, _vp, _vp]),
+    "d3_energy_forces_virial_noalloc": (_c_i32, [ctypes.POINTER(d3_params),
+                                                 ctypes.POINTER(d3_table), _c_i64, _vp, _vp,
+                                                 _vp, _vp, _vp, _vp, _vp, _vp, _c_u32, _vp]),
 }
 
 EXPORTS = tuple(_SIGS)
@@ -208,6 +211,23 @@ def d3_evaluate(ctx, pos, energy, forces=None, virial=None, atom_energy=None,
     out = d3_outputs(p(energy), p(forces), p(virial), p(atom_energy), p(atom_virial),
                      p(velocities), p(heat_current))
     _check(lib().d3_evaluate(ctx, _ptr(pos), ctypes.byref(out), int(flags), _stream(stream)))
+
+
+D3_NOALLOC_MAX_ATOMS = 4096
+
+
+def d3_energy_forces_virial_noalloc(params, table, pos, types, cell, pbc, energy, forces=None,
+                                    virial=None, atom_energy=None, flags=0, stream=None):
+    """One evaluation with no context and no allocation (the static-scratch
+    entry point); device tensors in, synchronises before returning."""
+    t = _Table(table)
+    cell = np.ascontiguousarray(cell, dtype=np.float64).reshape(9)
+    pbc = np.ascontiguousarray(pbc, dtype=np.int32).reshape(3)
+    n = int(pos.shape[0]) if pos is not None else 0
+    _check(lib().d3_energy_forces_virial_noalloc(
+        ctypes.byref(params), ctypes.byref(t.c), n, _ptr(pos), _ptr(types), cell.ctypes.data,
+        pbc.ctypes.data, _ptr(energy), _ptr(forces), _ptr(virial), _ptr(atom_energy),
+        int(flags), _stream(stream)))
 
 
 def d3_bin_plan(cell, pbc, rlist, rcn, n, max_rows=8192):

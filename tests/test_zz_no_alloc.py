@@ -1,0 +1,92 @@
+"""The allocation-free entry point (static device scratch, no context)
+against d3_energy_forces_virial on the same inputs, through the C ABI: two
+calls in a row, the second with a smaller input, then a call that exceeds
+the atom limit (refused on the host) and one in the precision form."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import d3_ref as R
+
+pytestmark = pytest.mark.gpu
+
+TAB = synth.make_table()
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    return torch
+
+
+def _context_result(s, mode):
+    from paper_2310_05279_amd import d3
+    calc = d3.D3(TAB, mode=mode)
+    calc.build(s["pos"], s["types"], s["cell"], s["pbc"])
+    out = calc.compute()
+    _torch().cuda.synchronize()
+    calc.status()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    calc.close()
+    return res
+
+
+def _noalloc_result(s, mode):
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    n = s["pos"].shape[0]
+    dev = torch.device("cuda", 0)
+    pos = torch.as_tensor(s["pos"], dtype=torch.float64, device=dev)
+    types = torch.as_tensor(s["types"], dtype=torch.int32, device=dev)
+    out = {"energy": torch.full((1,), 7.0, dtype=torch.float64, device=dev),
+           "forces": torch.full((n, 3), 7.0, dtype=torch.float64, device=dev),
+           "virial": torch.full((3, 3), 7.0, dtype=torch.float64, device=dev),
+           "atom_energy": torch.full((n,), 7.0, dtype=torch.float64, device=dev)}
+    prm = d3.make_params(mode=d3.MODES[mode])
+    d3.d3_energy_forces_virial_noalloc(prm, TAB, pos, types, s["cell"], s["pbc"],
+                                       out["energy"], out["forces"], out["virial"],
+                                       out["atom_energy"])
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("mode", ["plain", "prec"])
+def test_noalloc_matches_the_context_path_twice(mode):
+    """First a 3 000-atom MOF-like cell, then the 144-atom bilayer (smaller,
+    on the same static array): both bit for bit what the context path gives
+    (same kernels, same launch shapes), and within the plain gates of the
+    oracle on the second."""
+    big = synth.mof_like(3000, seed=31)
+    small = synth.bilayer_graphene()
+    for s, label in ((big, "3000-atom cell"), (small, "144-atom bilayer")):
+        print("noalloc %s %s" % (mode, label), flush=True)
+        want = _context_result(s, mode)
+        got = _noalloc_result(s, mode)
+        for k in want:
+            assert np.array_equal(got[k], want[k]), "%s: %s differs" % (label, k)
+    ref = R.d3(small["pos"], small["types"], small["cell"], small["pbc"], TAB)
+    n = small["pos"].shape[0]
+    assert abs(got["energy"][0] - ref["energy"]) / n <= 1e-6
+    assert np.abs(got["forces"] - ref["forces"]).max() <= (1e-5 if mode == "plain" else 1e-4)
+
+
+def test_noalloc_limits_are_refused():
+    """More atoms than the static limit is refused on the host with a clear
+    message; the surrogate mode (which needs a trained context) too."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    n = d3.D3_NOALLOC_MAX_ATOMS + 1
+    s = synth.mof_like(n, seed=3)
+    dev = torch.device("cuda", 0)
+    pos = torch.as_tensor(s["pos"], device=dev)
+    types = torch.as_tensor(s["types"], dtype=torch.int32, device=dev)
+    e = torch.zeros(1, dtype=torch.float64, device=dev)
+    with pytest.raises(d3.D3Error) as ei:
+        d3.d3_energy_forces_virial_noalloc(d3.make_params(), TAB, pos, types, s["cell"],
+                                           s["pbc"], e)
+    assert ei.value.code == d3.D3_ERR_INVALID_ARG and "limit" in str(ei.value)
+    with pytest.raises(d3.D3Error) as ei:
+        d3.d3_energy_forces_virial_noalloc(d3.make_params(mode=d3.D3_MODE_SURROGATE), TAB,
+                                           pos[:10], types[:10], s["cell"], s["pbc"], e)
+    assert ei.value.code == d3.D3_ERR_INVALID_ARG
