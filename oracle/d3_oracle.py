@@ -56,12 +56,28 @@ MAX_REF = 5
 
 
 class Params:
-    """Damping parameters and cutoffs (a2 and cutoffs in Angstrom)."""
+    """Damping parameters and cutoffs (a2 and cutoffs in Angstrom).
+
+    damping="bj" is Eq. 2 (Becke-Johnson).  damping="zero" is the other D3
+    damping the paper names and sets aside (Sec. II A, before Eq. 1), in its
+    definition by Grimme et al. (J. Chem. Phys. 132, 154104 (2010), the D3
+    reference the paper cites): each term -s_n C_n / r^n is multiplied by
+    f_n = 1 / (1 + 6 (r / (s_r,n R0))^(-alpha_n)), alpha_6 = 14,
+    alpha_8 = 16, with s_r,6 = rs6 and s_r,8 = rs8.
+
+    s9 != 0 adds the three-body Axilrod-Teller-Muto term of the same
+    reference (the paper also sets it aside) over triples whose three
+    distances are below r_atm (see atm_terms)."""
 
     def __init__(self, s6=1.0, a1=0.4289, s8=0.7875, a2=4.4407,
-                 r_pot=12.0, r_cn=6.0):
+                 r_pot=12.0, r_cn=6.0, damping="bj", rs6=1.217, rs8=1.0,
+                 s9=0.0, r_atm=None):
         self.s6, self.a1, self.s8, self.a2 = s6, a1, s8, a2
         self.r_pot, self.r_cn = r_pot, r_cn
+        assert damping in ("bj", "zero")
+        self.damping, self.rs6, self.rs8 = damping, rs6, rs8
+        self.s9 = s9
+        self.r_atm = r_cn if r_atm is None else r_atm
 
 
 def convert_table(table):
@@ -185,10 +201,33 @@ def c6_eq3(zi, zj, ni, nj, tab):
     return c6, dc6_dni, dc6_dnj
 
 
+ZERO_ALPHA6 = 14.0
+ZERO_ALPHA8 = 16.0
+
+
+def _zero_term(r2, c, s, sr, r0, n, alpha):
+    """One zero-damped term -s C f(r) / r^n, f = 1 / (1 + 6 (r/(sr R0))^-alpha):
+    its value, its r-derivative divided by r, and f / r^n."""
+    r = np.sqrt(r2)
+    q = (r / (sr * r0)) ** (-alpha)
+    f = 1.0 / (1.0 + 6.0 * q)
+    rn = r2 ** (n // 2)
+    e = -s * c * f / rn
+    # d/dr [f / r^n] = f' / r^n - n f / r^(n+1), with f' = 6 alpha q f^2 / r
+    de_r = -s * c * (6.0 * alpha * q * f * f - n * f) / (rn * r2)
+    return e, de_r, f / rn
+
+
 def pair_terms(r2, zi, zj, c6, tab, prm):
-    """Eq. 2 pair energy phi (both halves), d phi/dr divided by r, and
-    d phi / d C6, at fixed C6."""
+    """Pair energy phi (both halves), d phi/dr divided by r, and
+    d phi / d C6, at fixed C6: Eq. 2 (Becke-Johnson damping), or zero
+    damping (see Params)."""
     r0sq = tab["r0sq"][zi, zj]
+    if prm.damping == "zero":
+        r0 = np.sqrt(r0sq)
+        e6, d6, g6 = _zero_term(r2, c6, prm.s6, prm.rs6, r0, 6, ZERO_ALPHA6)
+        e8, d8, g8 = _zero_term(r2, c6 * r0sq, prm.s8, prm.rs8, r0, 8, ZERO_ALPHA8)
+        return e6 + e8, d6 + d8, -(prm.s6 * g6 + prm.s8 * r0sq * g8)
     rd = prm.a1 * np.sqrt(r0sq) + prm.a2
     r6 = r2 ** 3
     r8 = r2 ** 4
@@ -205,6 +244,103 @@ def pair_terms(r2, zi, zj, c6, tab, prm):
     return phi, dphi_r, dphi_dc6
 
 
+ATM_SR3 = 4.0 / 3.0
+ATM_ALPHA = 16.0
+
+
+def atm_triple(a, b, c, r0ab, r0bc, r0ca, prm):
+    """Geometry and damping of the three-body term of one triangle with
+    squared sides a = r_AB^2, b = r_BC^2, c = r_CA^2 (arrays):
+      g = (1 + 3 cos(A) cos(B) cos(C)) / (r_AB r_BC r_CA)^3 * f3,
+    where the cosine product is (a + c - b)(a + b - c)(b + c - a) / (8 abc)
+    (law of cosines) and f3 = 1 / (1 + 6 (rbar / (4/3 R0bar))^-16), rbar and
+    R0bar the geometric means of the three sides and of the three pair radii.
+    Returns g and its derivatives dg/da, dg/db, dg/dc."""
+    u = a * b * c
+    P = (a + c - b) * (a + b - c) * (b + c - a)
+    dP = ((a + b - c) * (b + c - a) + (a + c - b) * (b + c - a) - (a + c - b) * (a + b - c),
+          (a + c - b) * (b + c - a) - (a + b - c) * (b + c - a) + (a + c - b) * (a + b - c),
+          (a + b - c) * (b + c - a) - (a + c - b) * (b + c - a) + (a + c - b) * (a + b - c))
+    du = (b * c, a * c, a * b)
+    ang = 1.0 + 3.0 * P / (8.0 * u)
+    k0 = (ATM_SR3 ** 3 * r0ab * r0bc * r0ca) ** (ATM_ALPHA / 3.0)   # (sr3 R0bar)^16
+    q = k0 * u ** (-ATM_ALPHA / 6.0)                                # (rbar/(sr3 R0bar))^-16
+    f3 = 1.0 / (1.0 + 6.0 * q)
+    g = ang * u ** -1.5 * f3
+    out = []
+    for k in range(3):
+        dang = 3.0 / 8.0 * (dP[k] * u - P * du[k]) / (u * u)
+        du15 = -1.5 * u ** -2.5 * du[k]
+        df3 = 6.0 * f3 * f3 * q * (ATM_ALPHA / 6.0) * du[k] / u
+        out.append(dang * u ** -1.5 * f3 + ang * du15 * f3 + ang * u ** -1.5 * df3)
+    return g, out[0], out[1], out[2]
+
+
+def atm_terms(n, types, tab, prm, i, j, d, cn, c6_fn=None):
+    """The three-body (Axilrod-Teller-Muto) term of D3 (Grimme et al. 2010),
+    which the paper sets aside: over every triangle of atom images whose
+    three sides are below r_atm,
+      E_ABC = s9 sqrt(C6_AB C6_BC C6_CA) (1 + 3 cos A cos B cos C)
+              / (r_AB r_BC r_CA)^3 f3,
+    with each C6 from Eq. 3 at the atoms' coordination numbers (positive
+    for an equilateral triangle: the triple-dipole repulsion).  Atom A
+    finds each triangle it belongs to as a pair of its own entries (B, C)
+    within r_atm whose third side is also below r_atm; each of the three
+    atoms takes a third of E_ABC (site energy and per-atom virial), its own
+    force and its own dE/dn.  Returns site energies, dE/dn, forces, the
+    virial and the per-atom virials."""
+    if c6_fn is None:
+        def c6_fn(zi, zj, ni, nj):
+            return c6_eq3(zi, zj, ni, nj, tab)
+    r2 = np.einsum("ek,ek->e", d, d)
+    ra2 = prm.r_atm * prm.r_atm
+    m = r2 < ra2
+    i, j, d = i[m], j[m], d[m]
+    order = np.argsort(i, kind="stable")
+    i, j, d = i[order], j[order], d[order]
+    starts = np.searchsorted(i, np.arange(n + 1))
+    atom_e = np.zeros(n)
+    dedn = np.zeros(n)
+    forces = np.zeros((n, 3))
+    atom_vir = np.zeros((n, 3, 3))
+    r0 = np.sqrt(tab["r0sq"])
+    for A in range(n):
+        s0, s1 = starts[A], starts[A + 1]
+        k = s1 - s0
+        if k < 2:
+            continue
+        e1, e2 = np.triu_indices(k, 1)
+        dab, dac = d[s0 + e1], d[s0 + e2]
+        dbc = dac - dab
+        a = np.einsum("ek,ek->e", dab, dab)
+        c = np.einsum("ek,ek->e", dac, dac)
+        b = np.einsum("ek,ek->e", dbc, dbc)
+        keep = b < ra2
+        e1, e2, dab, dac, dbc, a, b, c = (x[keep] for x in (e1, e2, dab, dac, dbc, a, b, c))
+        if e1.size == 0:
+            continue
+        B, C = j[s0 + e1], j[s0 + e2]
+        zA = np.full(B.size, types[A])
+        zB, zC = types[B], types[C]
+        nA = np.full(B.size, cn[A])
+        cab, dab_dnA, _ = c6_fn(zA, zB, nA, cn[B])
+        cac, dac_dnA, _ = c6_fn(zA, zC, nA, cn[C])
+        cbc, _, _ = c6_fn(zB, zC, cn[B], cn[C])
+        g, ga, gb, gc = atm_triple(a, b, c, r0[zA, zB], r0[zB, zC], r0[zC, zA], prm)
+        cc = prm.s9 * np.sqrt(cab * cbc * cac)
+        E = cc * g
+        atom_e[A] = E.sum() / 3.0
+        dedn[A] = (0.5 * E * (dab_dnA / cab + dac_dnA / cac)).sum()
+        # a = |d_AB|^2 and c = |d_AC|^2 depend on r_A: dE/dr_A = -2 E_a d_AB - 2 E_c d_AC
+        forces[A] = 2.0 * ((cc * ga)[:, None] * dab + (cc * gc)[:, None] * dac).sum(0)
+        # W = -dE/d(strain) = -2 sum over the three sides of dE/d(side^2) side (x) side
+        w = -2.0 * (np.einsum("e,ea,eb->ab", cc * ga, dab, dab) +
+                    np.einsum("e,ea,eb->ab", cc * gb, dbc, dbc) +
+                    np.einsum("e,ea,eb->ab", cc * gc, dac, dac))
+        atom_vir[A] = w / 3.0
+    return atom_e, dedn, forces, atom_vir.sum(0), atom_vir
+
+
 def d3(pos, types, cell, pbc, table, prm=None, c6_fn=None):
     """Full FP64 evaluation.  Returns dict with energy, forces (N,3),
     virial (3,3), atom_energy (N), cn (N), dE/dn (N).
@@ -218,7 +354,7 @@ def d3(pos, types, cell, pbc, table, prm=None, c6_fn=None):
     pos = np.asarray(pos, dtype=np.float64)
     types = np.asarray(types, dtype=np.int64)
     n = pos.shape[0]
-    i, j, d = entries(pos, cell, pbc, max(prm.r_pot, prm.r_cn))
+    i, j, d = entries(pos, cell, pbc, max(prm.r_pot, prm.r_cn, prm.r_atm))
     return _evaluate(n, types, tab, prm, i, j, d, c6_fn=c6_fn)
 
 
@@ -241,6 +377,13 @@ def _evaluate(n, types, tab, prm, i, j, d, cn=None, c6_fn=None):
     for k in range(3):
         forces[:, k] += np.bincount(ip, weights=dphi_r * dp[:, k], minlength=n)
     vir = -0.5 * np.einsum("e,ea,eb->ab", dphi_r, dp, dp)
+    atom_vir3 = 0.0
+    if prm.s9 != 0.0:
+        ue3, g3, f3, w3, atom_vir3 = atm_terms(n, types, tab, prm, i, j, d, cn, c6_fn)
+        atom_e = atom_e + ue3
+        dedn = dedn + g3
+        forces += f3
+        vir = vir + w3
     # chain entries through the coordination numbers
     mc = r2 < prm.r_cn * prm.r_cn
     ic, jc, dc, r2c = i[mc], j[mc], d[mc], r2[mc]
@@ -258,6 +401,7 @@ def _evaluate(n, types, tab, prm, i, j, d, cn=None, c6_fn=None):
             atom_vir[:, a, b] = -0.5 * (
                 np.bincount(ip, weights=dphi_r * dp[:, a] * dp[:, b], minlength=n) +
                 np.bincount(ic, weights=coef * dc[:, a] * dc[:, b], minlength=n))
+    atom_vir = atom_vir + atom_vir3
     return {"energy": float(atom_e.sum()), "forces": forces, "virial": vir,
             "atom_energy": atom_e, "atom_virial": atom_vir, "cn": cn, "dedn": dedn}
 
@@ -275,14 +419,17 @@ def energy_only(pos, types, cell, pbc, table, prm=None):
     pos = np.asarray(pos, dtype=np.float64)
     types = np.asarray(types, dtype=np.int64)
     n = pos.shape[0]
-    i, j, d = entries(pos, cell, pbc, max(prm.r_pot, prm.r_cn))
+    i, j, d = entries(pos, cell, pbc, max(prm.r_pot, prm.r_cn, prm.r_atm))
     r2 = np.einsum("ek,ek->e", d, d)
     cn = coordination(n, types, tab, i, j, d, prm.r_cn)
     mp = r2 < prm.r_pot * prm.r_pot
     zi, zj = types[i[mp]], types[j[mp]]
     c6, _, _ = c6_eq3(zi, zj, cn[i[mp]], cn[j[mp]], tab)
     phi, _, _ = pair_terms(r2[mp], zi, zj, c6, tab, prm)
-    return 0.5 * phi.sum()
+    e = 0.5 * phi.sum()
+    if prm.s9 != 0.0:
+        e += atm_terms(n, types, tab, prm, i, j, d, cn)[0].sum()
+    return e
 
 
 def sampled(pos, types, cell, pbc, table, idx, prm=None, c6_fn=None):
@@ -296,6 +443,8 @@ def sampled(pos, types, cell, pbc, table, idx, prm=None, c6_fn=None):
     fixed by the images within R_pot + 2 R_cn of k, and the full definition
     restricted to that ball gives the exact result.  c6_fn: as in d3()."""
     prm = prm or Params()
+    if prm.s9 != 0.0:
+        raise NotImplementedError("the sampled mode covers the two-body terms only")
     tab = convert_table(table)
     if c6_fn is None:
         def c6_fn(zi, zj, ni, nj):

@@ -14,7 +14,12 @@
  *   n_i       Eq. 4 over entries with r < R_cn;
  *   C6        Eq. 3 per entry, the double sum over reference pairs with all
  *             exponents shifted by their maximum (the shift cancels);
- *   U_i, E    Eqs. 2 and 1 with C8 = C6 R0^2, R0^2 = 3 r2r4_i r2r4_j;
+ *   U_i, E    Eqs. 2 and 1 with C8 = C6 R0^2, R0^2 = 3 r2r4_i r2r4_j; or,
+ *             with zero damping, -s_n C_n f_n / r^n, f_n = 1 / (1 + 6 (r /
+ *             (s_r,n R0))^-alpha_n), alpha 14 and 16, and optionally the
+ *             three-body (Axilrod-Teller-Muto) term, both as defined by the
+ *             D3 reference the paper cites (Grimme et al. 2010) for the
+ *             variants the paper sets aside;
  *   F_i       exact -dE/dr_i: a direct term at fixed C6 plus the chain term
  *             through dE/dn (C6 depends on the coordination numbers);
  *   W         -dE/d(strain) = Eq. 7 summed over atoms;
@@ -284,7 +289,53 @@ typedef struct {
     const int *types, *n_ref;
     const double *cn_ref, *rcov, *c6, *r0sq;
     double s6, a1, s8, a2, rp2, rc2;
+    int zero;          /* 0: Becke-Johnson damping (Eq. 2); 1: zero damping */
+    double rs6, rs8;   /* zero damping: s_r,6, s_r,8 */
+    double s9, ra2;    /* three-body scale and cutoff squared */
 } phys;
+
+/* zero damping of -s C / r^n: f = 1 / (1 + 6 (r / (sr R0))^-alpha); returns
+ * the term's value, sets *de_r to its r-derivative over r and *g to f/r^n */
+static double zero_term(double r2, double c, double s, double sr, double r0, int n,
+                        double alpha, double *de_r, double *g)
+{
+    double r = sqrt(r2);
+    double q = pow(r / (sr * r0), -alpha);
+    double f = 1.0 / (1.0 + 6.0 * q);
+    double rn = pow(r2, 0.5 * n);
+    *de_r = -s * c * (6.0 * alpha * q * f * f - n * f) / (rn * r2);
+    *g = f / rn;
+    return -s * c * f / rn;
+}
+
+/* ATM geometry and damping of one triangle with squared sides a = AB^2,
+ * b = BC^2, c = CA^2 and pair radii r0ab, r0bc, r0ca:
+ * g = (1 + 3 cosA cosB cosC) / (r_AB r_BC r_CA)^3 f3 with the cosine
+ * product (a + c - b)(a + b - c)(b + c - a) / (8abc), f3 = 1 / (1 + 6
+ * (rbar / (4/3 R0bar))^-16) (geometric means); derivatives in ga, gb, gc */
+static double atm_g(double a, double b, double c, double r0ab, double r0bc, double r0ca,
+                    double *ga, double *gb, double *gc)
+{
+    const double alpha = 16.0, sr3 = 4.0 / 3.0;
+    double u = a * b * c;
+    double x = a + c - b, y = a + b - c, z = b + c - a;
+    double P = x * y * z;
+    double dP[3] = {y * z + x * z - x * y, x * z - y * z + x * y, y * z - x * z + x * y};
+    double du[3] = {b * c, a * c, a * b};
+    double ang = 1.0 + 3.0 * P / (8.0 * u);
+    double k0 = pow(sr3 * sr3 * sr3 * r0ab * r0bc * r0ca, alpha / 3.0);
+    double q = k0 * pow(u, -alpha / 6.0);
+    double f3 = 1.0 / (1.0 + 6.0 * q);
+    double u15 = pow(u, -1.5);
+    double *out[3] = {ga, gb, gc};
+    for (int k = 0; k < 3; k++) {
+        double dang = 3.0 / 8.0 * (dP[k] * u - P * du[k]) / (u * u);
+        double du15 = -1.5 * u15 / u * du[k];
+        double df3 = 6.0 * f3 * f3 * q * (alpha / 6.0) * du[k] / u;
+        *out[k] = dang * u15 * f3 + ang * du15 * f3 + ang * u15 * df3;
+    }
+    return ang * u15 * f3;
+}
 
 /* Eq. 4 */
 static double cn_atom(const phys *P, int i, const elist *l)
@@ -319,14 +370,24 @@ static long disp_atom(const phys *P, int i, const elist *l, const double *cn, do
                           P->cn_ref + MAXREF * zj,
                           P->c6 + ((size_t)zi * ne + zj) * MAXREF * MAXREF, cn[i], cn[j], &dci);
         double q = P->r0sq[zi * ne + zj];
-        double rd = P->a1 * sqrt(q) + P->a2;
-        double rd2 = rd * rd, rd6 = rd2 * rd2 * rd2, rd8 = rd6 * rd2;
-        double r6 = r2 * r2 * r2, r8 = r6 * r2;
-        double t6 = 1.0 / (r6 + rd6), t8 = 1.0 / (r8 + rd8);
-        double phi = -(P->s6 * c * t6 + P->s8 * c * q * t8);
-        double dphi_r = P->s6 * c * 6.0 * r2 * r2 * t6 * t6 + P->s8 * c * q * 8.0 * r6 * t8 * t8;
+        double phi, dphi_r, dphi_dc6;
+        if (P->zero) {
+            double d6, d8, g6, g8, r0 = sqrt(q);
+            phi = zero_term(r2, c, P->s6, P->rs6, r0, 6, 14.0, &d6, &g6) +
+                  zero_term(r2, c * q, P->s8, P->rs8, r0, 8, 16.0, &d8, &g8);
+            dphi_r = d6 + d8;
+            dphi_dc6 = -(P->s6 * g6 + P->s8 * q * g8);
+        } else {
+            double rd = P->a1 * sqrt(q) + P->a2;
+            double rd2 = rd * rd, rd6 = rd2 * rd2 * rd2, rd8 = rd6 * rd2;
+            double r6 = r2 * r2 * r2, r8 = r6 * r2;
+            double t6 = 1.0 / (r6 + rd6), t8 = 1.0 / (r8 + rd8);
+            phi = -(P->s6 * c * t6 + P->s8 * c * q * t8);
+            dphi_r = P->s6 * c * 6.0 * r2 * r2 * t6 * t6 + P->s8 * c * q * 8.0 * r6 * t8 * t8;
+            dphi_dc6 = -(P->s6 * t6 + P->s8 * q * t8);
+        }
         u += 0.5 * phi;
-        gi += -(P->s6 * t6 + P->s8 * q * t8) * dci;
+        gi += dphi_dc6 * dci;
         fx += dphi_r * d[0];
         fy += dphi_r * d[1];
         fz += dphi_r * d[2];
@@ -344,6 +405,64 @@ static long disp_atom(const phys *P, int i, const elist *l, const double *cn, do
     f_out[2] = fz;
     for (int k = 0; k < 6; k++) w_out[k] = w[k];
     return total;
+}
+
+/* three-body (ATM) term of atom i: every pair of its entries within
+ * r_atm whose third side is also within r_atm is a triangle it belongs to;
+ * adds a third of each triangle's energy and virial, the triangle's force
+ * on i and its dE/dn_i */
+static void atm_atom(const phys *P, int i, const elist *l, const double *cn, double *u_out,
+                     double *g_out, double *f, double *w)
+{
+    int ne = P->ne, zi = P->types[i];
+    double u = 0, gi = 0;
+    for (int e1 = 0; e1 < l->n; e1++) {
+        const double *d1 = l->d + 3 * e1;
+        double a = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2];
+        if (!(a < P->ra2)) continue;
+        int jb = l->j[e1], zb = P->types[jb];
+        double dab, cab = c6_eq3(P->n_ref[zi], P->cn_ref + MAXREF * zi, P->n_ref[zb],
+                                 P->cn_ref + MAXREF * zb,
+                                 P->c6 + ((size_t)zi * ne + zb) * MAXREF * MAXREF, cn[i], cn[jb],
+                                 &dab);
+        for (int e2 = e1 + 1; e2 < l->n; e2++) {
+            const double *d2 = l->d + 3 * e2;
+            double c = d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2];
+            if (!(c < P->ra2)) continue;
+            double bx = d2[0] - d1[0], by = d2[1] - d1[1], bz = d2[2] - d1[2];
+            double b = bx * bx + by * by + bz * bz;
+            if (!(b < P->ra2)) continue;
+            int jc = l->j[e2], zc = P->types[jc];
+            double dac, dummy;
+            double cac = c6_eq3(P->n_ref[zi], P->cn_ref + MAXREF * zi, P->n_ref[zc],
+                                P->cn_ref + MAXREF * zc,
+                                P->c6 + ((size_t)zi * ne + zc) * MAXREF * MAXREF, cn[i], cn[jc],
+                                &dac);
+            double cbc = c6_eq3(P->n_ref[zb], P->cn_ref + MAXREF * zb, P->n_ref[zc],
+                                P->cn_ref + MAXREF * zc,
+                                P->c6 + ((size_t)zb * ne + zc) * MAXREF * MAXREF, cn[jb], cn[jc],
+                                &dummy);
+            double ga, gb, gc;
+            double g = atm_g(a, b, c, sqrt(P->r0sq[zi * ne + zb]), sqrt(P->r0sq[zb * ne + zc]),
+                             sqrt(P->r0sq[zc * ne + zi]), &ga, &gb, &gc);
+            double cc = P->s9 * sqrt(cab * cbc * cac);
+            double E = cc * g;
+            u += E / 3.0;
+            gi += 0.5 * E * (dab / cab + dac / cac);
+            f[0] += 2.0 * cc * (ga * d1[0] + gc * d2[0]);
+            f[1] += 2.0 * cc * (ga * d1[1] + gc * d2[1]);
+            f[2] += 2.0 * cc * (ga * d1[2] + gc * d2[2]);
+            double ha = -2.0 * cc * ga / 3.0, hb = -2.0 * cc * gb / 3.0, hc = -2.0 * cc * gc / 3.0;
+            w[0] += ha * d1[0] * d1[0] + hb * bx * bx + hc * d2[0] * d2[0];
+            w[1] += ha * d1[0] * d1[1] + hb * bx * by + hc * d2[0] * d2[1];
+            w[2] += ha * d1[0] * d1[2] + hb * bx * bz + hc * d2[0] * d2[2];
+            w[3] += ha * d1[1] * d1[1] + hb * by * by + hc * d2[1] * d2[1];
+            w[4] += ha * d1[1] * d1[2] + hb * by * bz + hc * d2[1] * d2[2];
+            w[5] += ha * d1[2] * d1[2] + hb * bz * bz + hc * d2[2] * d2[2];
+        }
+    }
+    *u_out += u;
+    *g_out += gi;
 }
 
 /* chain term through the coordination numbers, added to f and w */
@@ -389,7 +508,8 @@ long d3ref_evaluate_mode(int n, const double *pos, const int *types,
                          const int *n_ref, const double *cn_ref,
                          const double *c6_au, const double *rcov,
                          const double *r2r4, double s6, double a1, double s8,
-                         double a2, double r_pot, double r_cn, int n_threads,
+                         double a2, double r_pot, double r_cn, int damping, double rs6,
+                         double rs8, double s9, double r_atm, int n_threads,
                          int use_cells, int n_eval, double *energy, double *forces,
                          double *virial, double *atom_energy, double *cn_out,
                          double *dedn_out, double *atom_virial)
@@ -400,7 +520,9 @@ long d3ref_evaluate_mode(int n, const double *pos, const int *types,
 #ifdef _OPENMP
     omp_set_num_threads(d3ref_threads_for(n_threads));
 #endif
+    const int atm = s9 != 0.0;
     double rmax = r_pot > r_cn ? r_pot : r_cn;
+    if (atm && r_atm > rmax) rmax = r_atm;
     double *c6 = (double *)malloc(sizeof(double) * ne * ne * MAXREF * MAXREF);
     double *r0sq = (double *)malloc(sizeof(double) * ne * ne);
     const double conv = HARTREE_EV * pow(BOHR_ANG, 6);
@@ -409,7 +531,7 @@ long d3ref_evaluate_mode(int n, const double *pos, const int *types,
         for (int f = 0; f < ne; f++)
             r0sq[e * ne + f] = 3.0 * r2r4[e] * r2r4[f] * BOHR_ANG * BOHR_ANG;
     phys P = {ne, types, n_ref, cn_ref, rcov, c6, r0sq, s6, a1, s8, a2,
-              r_pot * r_pot, r_cn * r_cn};
+              r_pot * r_pot, r_cn * r_cn, damping, rs6, rs8, s9, r_atm * r_atm};
 
     double *cn = (double *)calloc(n > 0 ? n : 1, sizeof(double));
     double *g = (double *)calloc(n > 0 ? n : 1, sizeof(double));
@@ -441,6 +563,11 @@ long d3ref_evaluate_mode(int n, const double *pos, const int *types,
         for (int i = 0; i < n; i++)
             total += disp_atom(&P, i, &L[i], cn, &ue[i], &g[i], fo + 3 * (size_t)i,
                                wv + 6 * (size_t)i);
+        if (atm) {
+#pragma omp parallel for schedule(dynamic, 16)
+            for (int i = 0; i < n; i++)
+                atm_atom(&P, i, &L[i], cn, &ue[i], &g[i], fo + 3 * (size_t)i, wv + 6 * (size_t)i);
+        }
 #pragma omp parallel for schedule(dynamic, 64)
         for (int i = 0; i < n; i++) chain_atom(&P, i, &L[i], g, fo + 3 * (size_t)i, wv + 6 * (size_t)i);
         for (int i = 0; i < n; i++) { free(L[i].j); free(L[i].d); }
@@ -464,9 +591,10 @@ long d3ref_evaluate_mode(int n, const double *pos, const int *types,
                                 fl[2] * cell[6 + m];
         }
         const int ne_atoms = (n_eval >= 0 && n_eval < n) ? n_eval : n;
-        cgrid gp, gc;
+        cgrid gp, gc, ga;
         grid_build(&gp, n, xw, sf, cell, pbc, r_pot);
         grid_build(&gc, n, xw, sf, cell, pbc, r_cn);
+        grid_build(&ga, n, xw, sf, cell, pbc, atm ? r_atm : r_cn);
 #pragma omp parallel
         {
             elist l = {0, 0, NULL, NULL};
@@ -481,6 +609,13 @@ long d3ref_evaluate_mode(int n, const double *pos, const int *types,
                 total += disp_atom(&P, i, &l, cn, &ue[i], &g[i], fo + 3 * (size_t)i,
                                    wv + 6 * (size_t)i);
             }
+            if (atm) {
+#pragma omp for schedule(dynamic, 16)
+                for (int i = 0; i < ne_atoms; i++) {
+                    grid_gather(&ga, i, r_atm, sf, &l);
+                    atm_atom(&P, i, &l, cn, &ue[i], &g[i], fo + 3 * (size_t)i, wv + 6 * (size_t)i);
+                }
+            }
 #pragma omp for schedule(dynamic, 64)
             for (int i = 0; i < ne_atoms; i++) {
                 grid_gather(&gc, i, r_cn, sf, &l);
@@ -491,6 +626,7 @@ long d3ref_evaluate_mode(int n, const double *pos, const int *types,
         }
         grid_free(&gp);
         grid_free(&gc);
+        grid_free(&ga);
         free(xw);
         free(sf);
     }
@@ -535,6 +671,7 @@ long d3ref_evaluate(int n, const double *pos, const int *types,
                     double *atom_virial)
 {
     return d3ref_evaluate_mode(n, pos, types, cell, pbc, ne, n_ref, cn_ref, c6_au, rcov, r2r4,
-                               s6, a1, s8, a2, r_pot, r_cn, n_threads, 0, n, energy, forces,
+                               s6, a1, s8, a2, r_pot, r_cn, 0, 1.217, 1.0, 0.0, r_cn, n_threads,
+                               0, n, energy, forces,
                                virial, atom_energy, cn_out, dedn_out, atom_virial);
 }

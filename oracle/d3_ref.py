@@ -36,7 +36,7 @@ def _load():
         I = ctypes.c_int
         lib.d3ref_evaluate_mode.restype = ctypes.c_long
         lib.d3ref_evaluate_mode.argtypes = [I, P, P, P, P, I, P, P, P, P, P,
-                                            D, D, D, D, D, D, I, I, I,
+                                            D, D, D, D, D, D, I, D, D, D, D, I, I, I,
                                             P, P, P, P, P, P, P]
         lib.d3ref_threads.restype = I
         lib.d3ref_threads_for.restype = I
@@ -55,7 +55,8 @@ def threads(n_threads=0):
 
 
 def d3(pos, types, cell, pbc, table, s6=1.0, a1=0.4289, s8=0.7875, a2=4.4407,
-       r_pot=12.0, r_cn=6.0, n_threads=0, cells=False, n_eval=None):
+       r_pot=12.0, r_cn=6.0, n_threads=0, cells=False, n_eval=None, damping="bj",
+       rs6=1.217, rs8=1.0, s9=0.0, r_atm=None):
     """Full FP64 evaluation; returns the same dict layout as
     d3_oracle.d3 plus the number of dispersion entries.  cells=False finds
     the entries by brute force over every atom and lattice translation;
@@ -63,7 +64,8 @@ def d3(pos, types, cell, pbc, table, s6=1.0, a1=0.4289, s8=0.7875, a2=4.4407,
     the mode for large cells).  n_threads=0 uses every OpenMP thread.
     n_eval (cell-list mode, timing only): run each pass for the first n_eval
     atoms alone, the work of n_eval atoms of the cell; the results are then
-    not the cell's."""
+    not the cell's.  damping="zero" and s9 (three-body term within r_atm,
+    default r_cn) select the variants, as in d3_oracle.Params."""
     lib = _load()
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     n = pos.shape[0]
@@ -88,7 +90,8 @@ def d3(pos, types, cell, pbc, table, s6=1.0, a1=0.4289, s8=0.7875, a2=4.4407,
     total = lib.d3ref_evaluate_mode(
         n, _ptr(pos), _ptr(types), _ptr(cellp), _ptr(pbcp), ne, _ptr(n_ref),
         _ptr(cn_ref), _ptr(c6), _ptr(rcov), _ptr(r2r4), s6, a1, s8, a2,
-        r_pot, r_cn, int(n_threads), 1 if cells else 0,
+        r_pot, r_cn, 1 if damping == "zero" else 0, rs6, rs8, s9,
+        r_cn if r_atm is None else r_atm, int(n_threads), 1 if cells else 0,
         n if n_eval is None else int(n_eval), _ptr(energy), _ptr(forces),
         _ptr(virial), _ptr(ae), _ptr(cn), _ptr(g), _ptr(av))
     if total < 0:

@@ -768,3 +768,197 @@ def test_md_oracle_energy_conservation_and_reversibility():
     p2, v2, _ = MD.run(p, -v, mass, c["types"], None, (0, 0, 0), tab, 200, 1.0, **prm)
     assert np.abs(p2 - c["pos"]).max() < 1e-12
     assert np.abs(v2 + vel).max() < 1e-14
+
+
+# ------------------------------------- zero damping and the ATM term ------
+# Both are the D3 variants the paper names and sets aside (Sec. II A, the
+# paragraph before Eq. 1); their definitions follow the D3 reference the
+# paper cites (Grimme et al., J. Chem. Phys. 132, 154104 (2010)).
+
+def _c6_r0(raw, za, zb):
+    c6 = raw["c6_ref"][za, zb, 0, 0] * HARTREE_EV * BOHR_ANG ** 6
+    r0 = np.sqrt(3.0 * raw["r2r4"][za] * raw["r2r4"][zb]) * BOHR_ANG
+    return c6, r0
+
+
+def test_zero_damping_dimer_closed_form():
+    """Zero damping on a single-reference dimer: E(r) = -s6 C6 f6 / r^6
+    - s8 C6 R0^2 f8 / r^8 with f_n = 1 / (1 + 6 (r / (s_r,n R0))^-alpha_n),
+    alpha = 14, 16.  At r = s_r,6 R0 the C6 term is damped to exactly 1/7,
+    at r = s_r,8 R0 the C8 term; far away both dampings go to 1.  A swapped
+    alpha, a missing factor 6 or R0 in place of s_r R0 fails one of these;
+    the force is -dE/dr of the closed form."""
+    raw = _table(force_k=1)
+    for za, zb in [(0, 4), (1, 1), (2, 3)]:
+        c6, r0 = _c6_r0(raw, za, zb)
+        prm6 = O.Params(damping="zero", s6=1.0, s8=0.0, rs6=1.217, r_pot=30.0)
+        r = 1.217 * r0
+        res = O.d3(*_dimer(za, zb, r), None, (0, 0, 0), raw, prm6)
+        assert res["energy"] == pytest.approx(-c6 / r ** 6 / 7.0, rel=1e-13)
+        prm8 = O.Params(damping="zero", s6=0.0, s8=0.722, rs8=1.0, r_pot=30.0)
+        r = r0
+        res = O.d3(*_dimer(za, zb, r), None, (0, 0, 0), raw, prm8)
+        assert res["energy"] == pytest.approx(-0.722 * c6 * r0 ** 2 / r ** 8 / 7.0, rel=1e-13)
+        prm = O.Params(damping="zero", s6=1.0, s8=0.722, rs6=1.217, rs8=1.0, r_pot=30.0)
+        for r in (1.5, 3.0, 5.5, 9.0):
+            res = O.d3(*_dimer(za, zb, r), None, (0, 0, 0), raw, prm)
+
+            def e_of(x):
+                f6 = 1.0 / (1.0 + 6.0 * (x / (1.217 * r0)) ** -14)
+                f8 = 1.0 / (1.0 + 6.0 * (x / r0) ** -16)
+                return -c6 * f6 / x ** 6 - 0.722 * c6 * r0 ** 2 * f8 / x ** 8
+            assert res["energy"] == pytest.approx(e_of(r), rel=1e-13)
+            h = 1e-6 * r
+            dE = (e_of(r + h) - e_of(r - h)) / (2 * h)
+            assert res["forces"][1, 0] == pytest.approx(-dE, rel=1e-7)
+        far = O.d3(*_dimer(za, zb, 28.0), None, (0, 0, 0), raw, prm)
+        assert far["energy"] == pytest.approx(-c6 / 28.0 ** 6 - 0.722 * c6 * r0 ** 2 / 28.0 ** 8,
+                                              rel=1e-9)
+
+
+def _atm_energy(pos, types, raw, **kw):
+    """Three-body part alone: E(s9) - E(s9 = 0) on a free cluster."""
+    on = O.d3(pos, types, None, (0, 0, 0), raw, O.Params(s9=1.0, **kw))
+    off = O.d3(pos, types, None, (0, 0, 0), raw, O.Params(s9=0.0, **kw))
+    return on, off
+
+
+@pytest.mark.parametrize("shape", ["equilateral", "collinear", "right"])
+def test_atm_triangle_closed_forms(shape):
+    """The ATM term of one homonuclear triangle (single reference, so every
+    C6 is the reference value): E = C6^(3/2) (1 + 3 cos A cos B cos C)
+    / (r_AB r_BC r_CA)^3 f3, f3 = 1 / (1 + 6 (rbar / (4/3 R0))^-16).  The
+    angle factor is 11/8 for an equilateral triangle (repulsive), -2 for a
+    collinear A-B-C with AB = BC, and 1 with a right angle; at rbar = 4/3 R0
+    the damping is exactly 1/7.  The site energies are thirds of E and the
+    total force is zero."""
+    raw = _table(force_k=1)
+    z = 1
+    c6, r0 = _c6_r0(raw, z, z)
+    types = np.array([z, z, z], np.int32)
+    for rbar in (4.0 / 3.0 * r0, 5.0):
+        if shape == "equilateral":
+            s = rbar
+            pos = np.array([[0, 0, 0], [s, 0, 0], [s / 2, s * np.sqrt(3) / 2, 0]])
+            sides, factor = (s, s, s), 11.0 / 8.0
+        elif shape == "collinear":
+            s = rbar / 2 ** (1 / 3)
+            pos = np.array([[0, 0, 0], [s, 0, 0], [2 * s, 0, 0]])
+            sides, factor = (s, s, 2 * s), -2.0
+        else:
+            s = rbar / 2 ** (1 / 6)
+            pos = np.array([[0, 0, 0], [s, 0, 0], [0, s, 0]])
+            sides, factor = (s, s, s * np.sqrt(2)), 1.0
+        on, off = _atm_energy(pos, types, raw, r_pot=15.0, r_cn=15.0, r_atm=15.0)
+        prod = sides[0] * sides[1] * sides[2]
+        f3 = 1.0 / (1.0 + 6.0 * (prod ** (1 / 3) / (4.0 / 3.0 * r0)) ** -16)
+        want = c6 ** 1.5 * factor / prod ** 3 * f3
+        if rbar == 4.0 / 3.0 * r0:
+            assert f3 == pytest.approx(1.0 / 7.0, rel=1e-14)
+        assert on["energy"] - off["energy"] == pytest.approx(want, rel=1e-12)
+        assert on["atom_energy"] - off["atom_energy"] == pytest.approx([want / 3] * 3, rel=1e-12)
+        assert np.abs(on["forces"].sum(0)).max() < 1e-12 * np.abs(on["forces"]).max()
+    if shape == "equilateral":
+        assert want > 0.0
+
+
+def test_atm_counts_each_triangle_once():
+    """Four atoms on a regular tetrahedron: the three-body energy is exactly
+    four equilateral-triangle terms, whichever vertex finds them; with the
+    cutoff below the edge it vanishes."""
+    raw = _table(force_k=1)
+    z = 2
+    c6, r0 = _c6_r0(raw, z, z)
+    s = 4.0
+    pos = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float) * s / np.sqrt(8)
+    types = np.full(4, z, np.int32)
+    on, off = _atm_energy(pos, types, raw, r_pot=10.0, r_cn=10.0, r_atm=10.0)
+    f3 = 1.0 / (1.0 + 6.0 * (s / (4.0 / 3.0 * r0)) ** -16)
+    assert on["energy"] - off["energy"] == pytest.approx(4 * c6 ** 1.5 * 11 / 8 / s ** 9 * f3,
+                                                         rel=1e-12)
+    short, off2 = _atm_energy(pos, types, raw, r_pot=10.0, r_cn=10.0, r_atm=3.99)
+    assert short["energy"] == off2["energy"]
+
+
+def _variant_params(**kw):
+    base = dict(damping="zero", s6=1.0, s8=0.722, rs6=1.217, rs8=1.0, s9=1.0)
+    base.update(kw)
+    return O.Params(**base)
+
+
+@pytest.mark.parametrize("damping", ["bj", "zero"])
+def test_atm_and_zero_damping_forces_are_the_gradient(damping):
+    """Forces with the three-body term (and either damping) against central
+    differences of the energy, on a cluster whose diameter lies within every
+    cutoff (so E is smooth) and whose coordination numbers vary, so the
+    chain term of the three-body coefficient through dE/dn is exercised."""
+    raw = _table()
+    c = synth.cluster(9, 2.6, dmin=1.3, seed=14)
+    prm = _variant_params(damping=damping, r_pot=20.0, r_cn=20.0, r_atm=20.0)
+    res = O.d3(c["pos"], c["types"], None, (0, 0, 0), raw, prm)
+    h = 1e-5
+    for k in (0, 4, 8):
+        for ax in range(3):
+            p = c["pos"].copy()
+            p[k, ax] += h
+            ep = O.energy_only(p, c["types"], None, (0, 0, 0), raw, prm)
+            p[k, ax] -= 2 * h
+            em = O.energy_only(p, c["types"], None, (0, 0, 0), raw, prm)
+            assert res["forces"][k, ax] == pytest.approx(-(ep - em) / (2 * h), abs=2e-8)
+    assert np.abs(res["forces"].sum(0)).max() < 1e-12
+
+
+def test_atm_virial_is_the_strain_derivative():
+    """With the three-body term on a small triclinic periodic cell (images
+    inside every cutoff): W = -dE/d(strain) by central differences of a
+    homogeneous strain of cell and positions, and sum_i W_i = W."""
+    raw = _table()
+    cell = np.array([[7.0, 0.0, 0.0], [1.2, 6.5, 0.0], [0.4, -0.8, 7.4]])
+    s = np.random.default_rng(9).uniform(0, 1, (5, 3))
+    pos = s @ cell
+    types = np.array([0, 1, 2, 3, 4], np.int32)
+    prm = _variant_params(damping="bj", r_pot=9.0, r_cn=6.0, r_atm=6.0)
+    res = O.d3(pos, types, cell, (1, 1, 1), raw, prm)
+    h = 1e-6
+    for a, b in [(0, 0), (1, 1), (0, 1), (2, 0), (1, 2)]:
+        eps = np.zeros((3, 3))
+        eps[a, b] = eps[b, a] = h if a != b else h
+        def strained(sign):
+            m = np.eye(3) + sign * eps
+            return O.energy_only(pos @ m.T, types, cell @ m.T, (1, 1, 1), raw, prm)
+        de = (strained(1) - strained(-1)) / (2 * h)
+        want = -de if a == b else -de / 2
+        assert res["virial"][a, b] == pytest.approx(want, rel=1e-6, abs=1e-9)
+    assert np.abs(res["atom_virial"].sum(0) - res["virial"]).max() < 1e-12 * np.abs(res["virial"]).max()
+
+
+def test_variants_off_reduce_to_eq2():
+    """s9 = 0 with BJ damping is exactly the two-body Eq. 2 evaluation."""
+    raw = _table()
+    m = synth.mof_like(300, seed=8)
+    a = O.d3(m["pos"], m["types"], m["cell"], m["pbc"], raw)
+    b = O.d3(m["pos"], m["types"], m["cell"], m["pbc"], raw, O.Params(s9=0.0, r_atm=6.0))
+    for k in ("energy", "forces", "virial", "atom_energy", "dedn"):
+        assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+
+
+def test_c_oracle_variants_match_numpy_oracle():
+    """The C oracle's zero damping and three-body term (both enumerations)
+    agree with the NumPy oracle on a skewed periodic cell with images
+    inside the cutoffs, a MOF-like cube and the bilayer."""
+    raw = _table()
+    cell = np.array([[7.0, 0.0, 0.0], [1.2, 6.5, 0.0], [0.4, -0.8, 7.4]])
+    s = np.random.default_rng(9).uniform(0, 1, (5, 3))
+    cases = [{"pos": s @ cell, "types": np.array([0, 1, 2, 3, 4], np.int32), "cell": cell,
+              "pbc": np.array([1, 1, 1])}, synth.mof_like(400, seed=12), synth.bilayer_graphene()]
+    for c in cases:
+        for damping, s8 in (("bj", 0.7875), ("zero", 0.722)):
+            kw = dict(damping=damping, s8=s8, s9=1.0, r_pot=10.0, r_cn=5.0, r_atm=5.0)
+            a = O.d3(c["pos"], c["types"], c["cell"], c["pbc"], raw, O.Params(**kw))
+            for cells in (False, True):
+                b = R.d3(c["pos"], c["types"], c["cell"], c["pbc"], raw, cells=cells, **kw)
+                assert b["energy"] == pytest.approx(a["energy"], rel=1e-12)
+                for k in ("forces", "virial", "atom_energy", "atom_virial", "dedn"):
+                    sc = max(np.abs(a[k]).max(), abs(a["energy"]))
+                    tol = 1e-10 if k == "dedn" else 1e-12
+                    assert np.abs(a[k] - b[k]).max() <= tol * sc, (damping, cells, k)
