@@ -427,6 +427,21 @@ def main():
             extra[name] = forms(big, steps, modes, weights)
             log("%s %s" % (name, json.dumps(extra[name])))
 
+        # the variants the paper sets aside: zero damping, the three-body term
+        # (r_atm = R_cn = 6 A) and both, on the headline cell, plain FP64
+        variants = {}
+        zero = dict(damping="zero", s6=1.0, s8=0.722, rs6=1.217, rs8=1.0)
+        for vname, kw in (("zero_damping", zero), ("bj_atm", dict(s9=1.0, r_atm=6.0)),
+                          ("zero_atm", dict(zero, s9=1.0, r_atm=6.0))):
+            run = Runner(system, table, "plain", **kw)
+            msv = run.timed(10, 2)
+            phv = run.phases(5)
+            run.close()
+            variants[vname] = {"atom_steps_per_s": n / (msv * 1e-3), "ms_per_step": msv,
+                               "phase_ms": phv}
+        extra["variants_mof_1M"] = variants
+        log("variants %s" % json.dumps(variants))
+
         # long cutoffs on the 24 000-atom cell, R_cn = R_pot / 2: speed, and the
         # force error of each cutoff against the 50 A result (plain FP64)
         sweep, f50 = {}, None

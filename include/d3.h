@@ -100,14 +100,34 @@ typedef enum d3_mode {
                               (single-point evaluations).  List overflow is
                               then reported by d3_status, as after a build */
 
-/* Damping parameters (Eq. 2) and cutoffs.  a2, r_pot, r_cn, skin in
- * Angstrom; s6, a1, s8 dimensionless.  Requires r_pot > 0, r_cn > 0,
- * skin >= 0.  Lists hold pairs within r_pot + skin and r_cn + skin. */
+/* Two-body damping (d3_params.damping). */
+#define D3_DAMP_BJ 0   /* Becke-Johnson, Eq. 2 */
+#define D3_DAMP_ZERO 1 /* zero damping: -s_n C_n f_n / r^n with
+                          f_n = 1 / (1 + 6 (r / (s_r,n R0))^-alpha_n),
+                          alpha_6 = 14, alpha_8 = 16 (the variant the paper
+                          sets aside before Eq. 1, as defined by the D3
+                          reference it cites, Grimme et al. 2010) */
+
+/* Damping parameters (Eq. 2) and cutoffs.  a2, r_pot, r_cn, skin, r_atm in
+ * Angstrom; s6, a1, s8, rs6, rs8, s9 dimensionless.  Requires r_pot > 0,
+ * r_cn > 0, skin >= 0.  Lists hold pairs within r_pot + skin and r_cn +
+ * skin.  damping: D3_DAMP_BJ (uses a1, a2) or D3_DAMP_ZERO (uses rs6, rs8
+ * > 0; R0 as for BJ, sqrt(3 r2r4_i r2r4_j)).  s9 != 0 adds the three-body
+ * Axilrod-Teller-Muto term (also set aside by the paper; same reference):
+ * over triangles whose three sides are below r_atm (0 < r_atm <= r_cn),
+ * s9 sqrt(C6_AB C6_BC C6_CA) (1 + 3 cos A cos B cos C) / (r_AB r_BC
+ * r_CA)^3 f3, f3 = 1 / (1 + 6 (rbar / (4/3 R0bar))^-16) with rbar and
+ * R0bar the geometric means of the sides and of the pair radii, C6 from
+ * Eq. 3 (exact in every mode), its CN dependence carried into the forces;
+ * each atom of a triangle takes a third of its energy and virial. */
 typedef struct d3_params {
     double s6, a1, s8, a2;
     double r_pot, r_cn, skin;
-    int32_t mode; /* d3_mode */
-    int32_t reserved;
+    int32_t mode;    /* d3_mode */
+    int32_t damping; /* D3_DAMP_BJ or D3_DAMP_ZERO */
+    double rs6, rs8; /* zero damping: s_r,6 and s_r,8 */
+    double s9;       /* three-body scale; 0 = no three-body term */
+    double r_atm;    /* three-body cutoff, 0 < r_atm <= r_cn when s9 != 0 */
 } d3_params;
 
 /* Reference table (Eqs. 3-4, host memory, copied by d3_create):
@@ -245,9 +265,9 @@ int d3_bin_plan(const double *cell, const int32_t *pbc, double rlist,
  * each group of launches: 0 binning and counting sort of a neighbour
  * build, 1 position update, 2 CN and weights, 3 dispersion pass, 4 chain
  * pass with the final reductions, 5 list construction of a neighbour build
- * (a build is phases 0 and 5).  enable = 1 starts (and clears) the
- * accumulation, 0 stops it. */
-#define D3_N_PHASES 6
+ * (a build is phases 0 and 5), 6 three-body pass.  enable = 1 starts (and
+ * clears) the accumulation, 0 stops it. */
+#define D3_N_PHASES 7
 int d3_set_timing(d3_ctx *ctx, int32_t enable);
 
 /* Summed milliseconds and number of timed calls per phase since timing was

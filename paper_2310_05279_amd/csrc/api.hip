@@ -403,6 +403,7 @@ int alloc_atoms(d3_ctx* c, int64_t n)
     const size_t nb = (size_t)max_pass_blocks();
     D3CHK(ensure(c->vpart, nb * 8 * sizeof(double)));
     D3CHK(ensure(c->vpart2, nb * 8 * sizeof(double)));
+    D3CHK(ensure(c->vpart3, nb * 8 * sizeof(double)));
     return D3_OK;
 }
 
@@ -592,6 +593,14 @@ int check_params_table(const d3_params* prm, const d3_table* tab)
         return fail(D3_ERR_INVALID_ARG, "non-finite damping parameter");
     if (prm->mode < D3_MODE_PLAIN_F64 || prm->mode > D3_MODE_LITERAL)
         return fail(D3_ERR_INVALID_ARG, "unknown mode %d", prm->mode);
+    if (prm->damping != D3_DAMP_BJ && prm->damping != D3_DAMP_ZERO)
+        return fail(D3_ERR_INVALID_ARG, "unknown damping %d", prm->damping);
+    if (prm->damping == D3_DAMP_ZERO &&
+        !(prm->rs6 > 0.0 && prm->rs8 > 0.0 && std::isfinite(prm->rs6) && std::isfinite(prm->rs8)))
+        return fail(D3_ERR_INVALID_ARG, "zero damping needs finite rs6 > 0 and rs8 > 0");
+    if (!std::isfinite(prm->s9)) return fail(D3_ERR_INVALID_ARG, "non-finite s9");
+    if (prm->s9 != 0.0 && !(prm->r_atm > 0.0 && prm->r_atm <= prm->r_cn))
+        return fail(D3_ERR_INVALID_ARG, "the three-body cutoff must satisfy 0 < r_atm <= r_cn");
     const int ne = tab->n_elem;
     if (ne < 1 || ne > MAXELEM) return fail(D3_ERR_INVALID_ARG, "n_elem=%d outside 1..%d", ne, MAXELEM);
     if (!tab->n_ref || !tab->cn_ref || !tab->c6_ref || !tab->rcov || !tab->r2r4)
@@ -621,7 +630,9 @@ int check_params_table(const d3_params* prm, const d3_table* tab)
 
 // The table in eV and Angstrom (FP64, on the host): per-element data, the
 // C6 reference grid [MAXELEM][MAXELEM][MAXREF][MAXREF] and per element
-// pair (Rd^6, Rd^8, R0^2, s8 R0^2), Rd = a1 R0 + a2 (Eq. 2).
+// pair the damping constants: (Rd^6, Rd^8, R0^2, s8 R0^2), Rd = a1 R0 + a2
+// (Eq. 2), or with zero damping (6 (rs6 R0)^14, 6 (rs8 R0)^16, R0^2,
+// s8 R0^2).
 void convert_table(const d3_params* prm, const d3_table* tab, ElemTab& et, double* c6,
                    double4* pc)
 {
@@ -642,9 +653,17 @@ void convert_table(const d3_params* prm, const d3_table* tab, ElemTab& et, doubl
                     c6[((size_t)(e * MAXELEM + f) * MAXREF + a) * MAXREF + b] =
                         tab->c6_ref[((e * ne + f) * MAXREF + a) * MAXREF + b] * conv;
             const double r0sq = 3.0 * tab->r2r4[e] * tab->r2r4[f] * BOHR_ANG * BOHR_ANG;
-            const double rd = prm->a1 * std::sqrt(r0sq) + prm->a2;
-            const double rd2 = rd * rd, rd6 = rd2 * rd2 * rd2;
-            pc[e * MAXELEM + f] = make_double4(rd6, rd6 * rd2, r0sq, prm->s8 * r0sq);
+            if (prm->damping == D3_DAMP_ZERO) {
+                // f_6 / r^6 = x^4 / (x^7 + K6) and f_8 / r^8 = x^4 / (x^8 + K8)
+                // with x = r^2, K6 = 6 (rs6 R0)^14, K8 = 6 (rs8 R0)^16
+                const double a6 = prm->rs6 * prm->rs6 * r0sq, a8 = prm->rs8 * prm->rs8 * r0sq;
+                pc[e * MAXELEM + f] = make_double4(6.0 * std::pow(a6, 7), 6.0 * std::pow(a8, 8),
+                                                   r0sq, prm->s8 * r0sq);
+            } else {
+                const double rd = prm->a1 * std::sqrt(r0sq) + prm->a2;
+                const double rd2 = rd * rd, rd6 = rd2 * rd2 * rd2;
+                pc[e * MAXELEM + f] = make_double4(rd6, rd6 * rd2, r0sq, prm->s8 * r0sq);
+            }
         }
     }
 }
@@ -951,6 +970,8 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
     if (mode == D3_MODE_SURROGATE) {
         if (!c->sur || !c->sur->trained)
             return fail(D3_ERR_NOT_TRAINED, "surrogate mode before training or loading weights");
+        if (c->prm.damping != D3_DAMP_BJ)
+            return fail(D3_ERR_INVALID_ARG, "the surrogate pass implements Becke-Johnson damping only");
         D3CHK(alloc_proj(c, D3_MODE_PREC_F32));
         cn_mode = D3_MODE_PREC_F32;  // surrogate needs float CNs; exact fallback uses Pf
     }
@@ -960,6 +981,9 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
     sc.s8 = c->prm.s8;
     sc.rp2 = c->prm.r_pot * c->prm.r_pot;
     sc.rc2 = c->prm.r_cn * c->prm.r_cn;
+    sc.zero = c->prm.damping == D3_DAMP_ZERO ? 1 : 0;
+    sc.rs6sq = c->prm.rs6 * c->prm.rs6;
+    sc.rs8sq = c->prm.rs8 * c->prm.rs8;
     phase_mark(c, PH_PAIR, s);
     int na = 0;
     if (mode == D3_MODE_SURROGATE) {
@@ -981,6 +1005,19 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
         HIPCHK(hipGetLastError());
     }
     phase_mark(c, PH_PAIR, s);
+    // the three-body term adds to U, G, the direct forces and (per atom) Vp
+    int n3 = 0;
+    if (c->prm.s9 != 0.0) {
+        phase_mark(c, PH_ATM, s);
+        n3 = launch_atm(n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img, g.img_bits,
+                        c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c,
+                        c->d_tab.as<ElemTab>(), c->d_c6.as<double>(), c->d_pc.as<double4>(),
+                        c->prm.s9, c->prm.r_atm * c->prm.r_atm, c->w.as<double>(),
+                        c->wd.as<double>(), c->Fp.as<double>(), c->U.as<double>(),
+                        c->G.as<double>(), Vp, c->vpart3.as<double>(), s);
+        phase_mark(c, PH_ATM, s);
+        HIPCHK(hipGetLastError());
+    }
     phase_mark(c, PH_CHAIN, s);
     const bool f64 = mode == D3_MODE_PLAIN_F64 || mode == D3_MODE_LITERAL;
     const int nb = launch_chain(f64 ? D3_MODE_PLAIN_F64 : D3_MODE_PREC_F32, n,
@@ -990,7 +1027,8 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
                  c->perm.as<int>(), forces, atom_energy, Vp, vel, atom_virial, heat_current,
                  acc, c->vpart2.as<double>(), s);
     HIPCHK(hipGetLastError());
-    launch_final(na, c->vpart.as<double>(), nb, c->vpart2.as<double>(), energy, virial, acc, s);
+    launch_final(na, c->vpart.as<double>(), nb, c->vpart2.as<double>(), n3,
+                 c->vpart3.as<double>(), energy, virial, acc, s);
     phase_mark(c, PH_CHAIN, s);
     HIPCHK(hipGetLastError());
     return D3_OK;

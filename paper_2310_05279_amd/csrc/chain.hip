@@ -162,11 +162,13 @@ k_chain(int n, const double4* __restrict__ pos_s, const double4* __restrict__ im
     block_partials(vals, part);
 }
 
-// Energy (Eq. 1) and virial from the workgroup partials of both passes,
-// summed in a fixed order by one workgroup.
+// Energy (Eq. 1) and virial from the workgroup partials of the passes
+// (dispersion a, chain b, and the three-body pass c when nc > 0), summed in
+// a fixed order by one workgroup.
 __global__ void __launch_bounds__(1024)
 k_final(int na, const double* __restrict__ part_a, int nb, const double* __restrict__ part_b,
-        double* __restrict__ energy, double* __restrict__ virial, int accumulate)
+        int nc, const double* __restrict__ part_c, double* __restrict__ energy,
+        double* __restrict__ virial, int accumulate)
 {
     __shared__ double fin[1024 / WAVE][8];
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -199,6 +201,17 @@ k_final(int na, const double* __restrict__ part_a, int nb, const double* __restr
             acc[5] += sa[r] * a1[r].y + sb[r] * c1[r].y;
             acc[6] += sa[r] * a1[r].z + sb[r] * c1[r].z;
         }
+    }
+    for (int b = threadIdx.x; b < nc; b += 1024) {
+        const double4* p = (const double4*)(part_c + (size_t)b * 8);
+        const double4 x0 = p[0], x1 = p[1];
+        acc[0] += x0.x;
+        acc[1] += x0.y;
+        acc[2] += x0.z;
+        acc[3] += x0.w;
+        acc[4] += x1.x;
+        acc[5] += x1.y;
+        acc[6] += x1.z;
     }
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     wave_sums(acc);
@@ -277,11 +290,12 @@ int launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab, 
     return nblk;
 }
 
-void launch_final(int na, const double* part_a, int nb, const double* part_b, double* energy,
-                  double* virial, int accumulate, hipStream_t s)
+void launch_final(int na, const double* part_a, int nb, const double* part_b, int nc,
+                  const double* part_c, double* energy, double* virial, int accumulate,
+                  hipStream_t s)
 {
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, s, na, part_a, nb, part_b, energy, virial,
-                       accumulate);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, s, na, part_a, nb, part_b, nc, part_c,
+                       energy, virial, accumulate);
 }
 
 void launch_scatter_out(int n, const double* src, const int* perm, double* dst, hipStream_t s)

@@ -90,7 +90,7 @@ struct d3_ctx {
     d3::Buf list_p, cnt_p, list_c, cnt_c;
     int cap_p = 0, cap_c = 0;
     // per-atom results
-    d3::Buf cn, cnf, w, wd, P, Pf, G, Fp, U, Vp, vpart, vpart2;
+    d3::Buf cn, cnf, w, wd, P, Pf, G, Fp, U, Vp, vpart, vpart2, vpart3;
     // status
     d3::Buf status, maxcnt;
     int* h_status = nullptr;
@@ -112,7 +112,7 @@ struct d3_ctx {
         return {&d_tab, &d_c6, &d_pc, &bin_of, &shift, &count, &bin_start,
                 &scan_tmp, &perm_tmp, &perm, &slab, &pos_s, &shift_s, &ref_s, &type_copy,
                 &img_tab, &row_tab, &list_p, &cnt_p, &list_c, &cnt_c, &cn, &cnf, &w, &wd, &P,
-                &Pf, &G, &Fp, &U, &Vp, &vpart, &vpart2, &status, &maxcnt, &md_scratch};
+                &Pf, &G, &Fp, &U, &Vp, &vpart, &vpart2, &vpart3, &status, &maxcnt, &md_scratch};
     }
 };
 
@@ -137,7 +137,8 @@ int status_code(int bits);
 int alloc_proj(d3_ctx* c, int mode);
 
 // phase timing
-enum Phase { PH_BUILD = 0, PH_UPDATE = 1, PH_CN = 2, PH_PAIR = 3, PH_CHAIN = 4, PH_LIST = 5 };
+enum Phase { PH_BUILD = 0, PH_UPDATE = 1, PH_CN = 2, PH_PAIR = 3, PH_CHAIN = 4, PH_LIST = 5,
+             PH_ATM = 6 };
 void phase_mark(d3_ctx* c, int phase, hipStream_t s);  // call twice: begin, end
 int timing_flush(d3_ctx* c);
 

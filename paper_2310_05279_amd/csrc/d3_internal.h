@@ -78,6 +78,8 @@ struct ElemTab {
 struct PairScal {
     double s6, s8;
     double rp2, rc2;  // evaluation cutoffs squared (no skin)
+    int zero;           // zero damping (pair constants 6 (rs6 R0)^14, 6 (rs8 R0)^16, R0^2, s8 R0^2)
+    double rs6sq, rs8sq;  // zero damping: rs6^2, rs8^2
 };
 
 // ---- launchers (cells.hip) --------------------------------------------
@@ -133,8 +135,14 @@ int launch_chain(int mode, int n, const double4* pos_s, const double4* img_tab, 
                   const double* U, const int* perm, double* forces, double* atom_energy,
                   const double* Vp, const double* vel, double* atom_virial,
                   double* heat_current, int accumulate, double* part, hipStream_t s);
-void launch_final(int na, const double* part_a, int nb, const double* part_b, double* energy,
-                  double* virial, int accumulate, hipStream_t s);
+void launch_final(int na, const double* part_a, int nb, const double* part_b, int nc,
+                  const double* part_c, double* energy, double* virial, int accumulate,
+                  hipStream_t s);
+int launch_atm(int n, const double4* pos_s, const double4* img_tab, int n_img, int img_bits,
+               const uint32_t* list_c, const int* cnt_c, int cap_c, const ElemTab* tab,
+               const double* c6ref, const double4* pc, double s9, double ra2, const double* w,
+               const double* wd, double* Fp, double* U, double* G, double* Vp, double* part,
+               hipStream_t s);
 void launch_scatter_out(int n, const double* src, const int* perm, double* dst, hipStream_t s);
 
 }  // namespace d3

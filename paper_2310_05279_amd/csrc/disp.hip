@@ -45,22 +45,40 @@ __device__ __forceinline__ double recip(double x)
     return fma(y, e, y);
 }
 
-// Eq. 2 for one entry in FP64 at fixed C6: phi = -C6 gg with
-// gg = s6 / (r^6 + Rd^6) + s8 R0^2 / (r^8 + Rd^8) (c = Rd^6, Rd^8, R0^2,
-// s8 R0^2), and dphi_r = phi'(r) / r.
+// The damped pair energy of one entry in FP64 at fixed C6: phi = -C6 gg,
+// and dphi_r = phi'(r) / r.  With x = r^2:
+//  Becke-Johnson (Eq. 2), c = (Rd^6, Rd^8, R0^2, s8 R0^2):
+//    gg = s6 / (x^3 + Rd^6) + s8 R0^2 / (x^4 + Rd^8);
+//  zero damping, c = (K6, K8, R0^2, s8 R0^2), K6 = 6 (rs6 R0)^14,
+//  K8 = 6 (rs8 R0)^16: f_n / r^n = x^4 / (x^(n/2+4) + K_n), so
+//    gg = x^4 (s6 / (x^7 + K6) + s8 R0^2 / (x^8 + K8)) and
+//    dphi_r = -2 C6 x^3 (s6 t6^2 (4 K6 - 3 x^7) + s8 R0^2 t8^2 (4 K8 - 4 x^8)).
+// Both denominators come from one reciprocal of their product.
 struct BJ {
     double gg, dphi_r;
 };
-__device__ __forceinline__ BJ bj_f64(double c6, double r2, const double4& c, double s6)
+template <bool ZERO>
+__device__ __forceinline__ BJ damp_f64(double c6, double r2, const double4& c, double s6)
 {
     const double r4 = r2 * r2, r6 = r4 * r2, r8 = r4 * r4;
-    const double A = r6 + c.x, B = r8 + c.y;
-    const double inv = recip(A * B);
-    const double t6 = B * inv, t8 = A * inv;
-    const double a6 = s6 * t6, a8 = c.w * t8;
     BJ o;
-    o.gg = a6 + a8;
-    o.dphi_r = c6 * (6.0 * a6 * r4 * t6 + 8.0 * a8 * r6 * t8);
+    if constexpr (ZERO) {
+        const double x7 = r8 * r6, x8 = r8 * r8;
+        const double A = x7 + c.x, B = x8 + c.y;
+        const double inv = recip(A * B);
+        const double t6 = B * inv, t8 = A * inv;
+        const double a6 = s6 * t6, a8 = c.w * t8;
+        o.gg = r8 * (a6 + a8);
+        o.dphi_r = -2.0 * c6 * r6 *
+                   (a6 * t6 * (4.0 * c.x - 3.0 * x7) + a8 * t8 * (4.0 * c.y - 4.0 * x8));
+    } else {
+        const double A = r6 + c.x, B = r8 + c.y;
+        const double inv = recip(A * B);
+        const double t6 = B * inv, t8 = A * inv;
+        const double a6 = s6 * t6, a8 = c.w * t8;
+        o.gg = a6 + a8;
+        o.dphi_r = c6 * (6.0 * a6 * r4 * t6 + 8.0 * a8 * r6 * t8);
+    }
     return o;
 }
 
@@ -106,7 +124,7 @@ __device__ __forceinline__ int rec_species(const Nbr<false>& nb)
 
 // AV: also the direct part of each atom's virial (Eq. 7), the six
 // components of sum over its entries of -1/2 phi'(r) r (x) r / r, to Vp.
-template <bool F32, bool IMG, bool AV>
+template <bool F32, bool IMG, bool AV, bool ZERO>
 __global__ void __launch_bounds__(BLOCK)
 k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_tab, int n_img,
        int img_bits, const uint32_t* __restrict__ list_p, const int* __restrict__ cnt_p, int cap_p,
@@ -212,7 +230,7 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
                 }
                 c6 = in ? c6 : 0.0;
                 dc6 = in ? dc6 : 0.0;
-                const BJ q = bj_f64(c6, r2, c, sc.s6);
+                const BJ q = damp_f64<ZERO>(c6, r2, c, sc.s6);
                 ue = fma(-0.5 * c6, q.gg, ue);
                 g = fma(-q.gg, dc6, g);
                 fx = fma(q.dphi_r, dx, fx);
@@ -232,12 +250,31 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
                 c6 = in ? c6 : 0.0f;
                 dc6 = in ? dc6 : 0.0f;
                 const float x = (float)dx, y = (float)dy, zz = (float)dz;
-                const float q2 = (float)r2;
-                const float r4 = q2 * q2, r6 = r4 * q2, r8 = r4 * r4;
-                const float t6 = __frcp_rn(r6 + (float)c.x), t8 = __frcp_rn(r8 + (float)c.y);
-                const float a6 = (float)sc.s6 * t6, a8 = (float)c.w * t8;
-                const float gg = a6 + a8;
-                const float dphi_r = c6 * (6.0f * a6 * r4 * t6 + 8.0f * a8 * r6 * t8);
+                float gg, dphi_r;
+                if constexpr (ZERO) {
+                    // in powers of 1/r^2 (no overflow of r^16 in FP32): with
+                    // q_n = ((rs_n R0)^2 / r^2)^(n/2+4) and f_n = 1 / (1 + 6 q_n),
+                    // gg = s6 f6 / r^6 + s8 R0^2 f8 / r^8 and
+                    // dphi_r = -2 C6 [s6 f6 (42 f6 q6 - 3) / r^8
+                    //                 + s8 R0^2 f8 (48 f8 q8 - 4) / r^10]
+                    const float iy = __frcp_rn(in ? (float)r2 : 1.0f);
+                    const float b6 = (float)(sc.rs6sq * c.z) * iy, b8 = (float)(sc.rs8sq * c.z) * iy;
+                    const float b62 = b6 * b6, b82 = b8 * b8, b84 = b82 * b82;
+                    const float q6 = b62 * b62 * b62 * b6, q8 = b84 * b84;
+                    const float f6 = __frcp_rn(1.0f + 6.0f * q6), f8 = __frcp_rn(1.0f + 6.0f * q8);
+                    const float y2 = iy * iy, y3 = y2 * iy, y4 = y2 * y2;
+                    const float a6 = (float)sc.s6 * f6, a8 = (float)c.w * f8;
+                    gg = a6 * y3 + a8 * y4;
+                    dphi_r = -2.0f * c6 *
+                             (a6 * y4 * (42.0f * f6 * q6 - 3.0f) + a8 * y4 * iy * (48.0f * f8 * q8 - 4.0f));
+                } else {
+                    const float q2 = (float)r2;
+                    const float r4 = q2 * q2, r6 = r4 * q2, r8 = r4 * r4;
+                    const float t6 = __frcp_rn(r6 + (float)c.x), t8 = __frcp_rn(r8 + (float)c.y);
+                    const float a6 = (float)sc.s6 * t6, a8 = (float)c.w * t8;
+                    gg = a6 + a8;
+                    dphi_r = c6 * (6.0f * a6 * r4 * t6 + 8.0f * a8 * r6 * t8);
+                }
                 ue += (double)(-0.5f * c6 * gg);
                 g += (double)(-gg * dc6);
                 fx += (double)(dphi_r * x);
@@ -309,7 +346,7 @@ k_pair(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img
 // weights, S = sum of weight x C6_ref and ' the derivative in n_i.  It
 // reads the CNs, not the factorised weights, and is otherwise the FP64
 // dispersion pass (one wave per atom, sums gathered onto the atom).
-template <bool IMG, bool AV>
+template <bool IMG, bool AV, bool ZERO>
 __global__ void __launch_bounds__(BLOCK)
 k_pair_lit(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_tab,
            int n_img, int img_bits, const uint32_t* __restrict__ list_p,
@@ -387,7 +424,7 @@ k_pair_lit(int n, const double4* __restrict__ pos_s, const double4* __restrict__
             double dc6 = (Sd - c6 * Zd) / Z;
             c6 = in ? c6 : 0.0;
             dc6 = in ? dc6 : 0.0;
-            const BJ q = bj_f64(c6, r2, s_pc[zi * MAXELEM + zj], sc.s6);
+            const BJ q = damp_f64<ZERO>(c6, r2, s_pc[zi * MAXELEM + zj], sc.s6);
             ue = fma(-0.5 * c6, q.gg, ue);
             g = fma(-q.gg, dc6, g);
             fx = fma(q.dphi_r, dx, fx);
@@ -425,20 +462,24 @@ int launch_pair_lit(int n, const double4* pos_s, const double4* img_tab, int n_i
     if (n <= 0) return 0;
     const bool lds = n_img <= IMG_LDS;
     int nblk = 0;
-#define D3_LIT(I, A)                                                                           \
+#define D3_LIT(I, A, Z)                                                                        \
     {                                                                                          \
-        nblk = pass_blocks((const void*)&k_pair_lit<I, A>, n);                                 \
-        hipLaunchKernelGGL((k_pair_lit<I, A>), dim3(nblk), dim3(BLOCK), 0, s, n, pos_s,        \
+        nblk = pass_blocks((const void*)&k_pair_lit<I, A, Z>, n);                              \
+        hipLaunchKernelGGL((k_pair_lit<I, A, Z>), dim3(nblk), dim3(BLOCK), 0, s, n, pos_s,     \
                            img_tab, n_img, img_bits, list_p, cnt_p, cap_p, tab, c6ref, pc, sc, \
                            cn, Fp, U, G, Vp, part);                                            \
     }
+#define D3_LIT_Z(I, A)          \
+    if (sc.zero) D3_LIT(I, A, true) \
+    else D3_LIT(I, A, false)
     if (Vp) {
-        if (lds) D3_LIT(true, true)
-        else D3_LIT(false, true)
+        if (lds) D3_LIT_Z(true, true)
+        else D3_LIT_Z(false, true)
     } else {
-        if (lds) D3_LIT(true, false)
-        else D3_LIT(false, false)
+        if (lds) D3_LIT_Z(true, false)
+        else D3_LIT_Z(false, false)
     }
+#undef D3_LIT_Z
 #undef D3_LIT
     return nblk;
 }
@@ -452,13 +493,16 @@ int launch_pair(int mode, int n, const double4* pos_s, const double4* img_tab, i
     if (n <= 0) return 0;
     const bool lds = n_img <= IMG_LDS;
     int nblk = 0;
-#define D3_PAIR(F, I, A)                                                                        \
+#define D3_PAIR_(F, I, A, Z)                                                                    \
     {                                                                                           \
-        nblk = pass_blocks((const void*)&k_pair<F, I, A>, n);                                   \
-        hipLaunchKernelGGL((k_pair<F, I, A>), dim3(nblk), dim3(BLOCK), 0, s, n, pos_s, img_tab, \
-                           n_img, img_bits, list_p, cnt_p, cap_p, tab, c6ref, pc, sc, w, wd, W, \
-                           Wf, Fp, U, G, Vp, part);                                             \
+        nblk = pass_blocks((const void*)&k_pair<F, I, A, Z>, n);                                \
+        hipLaunchKernelGGL((k_pair<F, I, A, Z>), dim3(nblk), dim3(BLOCK), 0, s, n, pos_s,       \
+                           img_tab, n_img, img_bits, list_p, cnt_p, cap_p, tab, c6ref, pc, sc,  \
+                           w, wd, W, Wf, Fp, U, G, Vp, part);                                   \
     }
+#define D3_PAIR(F, I, A)              \
+    if (sc.zero) D3_PAIR_(F, I, A, true) \
+    else D3_PAIR_(F, I, A, false)
     const bool prec = mode == D3_MODE_PREC_F32;
     if (Vp) {
         if (prec) {
@@ -478,6 +522,7 @@ int launch_pair(int mode, int n, const double4* pos_s, const double4* img_tab, i
         }
     }
 #undef D3_PAIR
+#undef D3_PAIR_
     return nblk;
 }
 

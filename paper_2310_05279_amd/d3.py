@@ -47,10 +47,16 @@ _c_u64 = ctypes.c_uint64
 _vp = ctypes.c_void_p
 
 
+D3_DAMP_BJ = 0
+D3_DAMP_ZERO = 1
+DAMPINGS = {"bj": 0, "zero": 1}
+
+
 class d3_params(ctypes.Structure):
     _fields_ = [("s6", _c_d), ("a1", _c_d), ("s8", _c_d), ("a2", _c_d),
                 ("r_pot", _c_d), ("r_cn", _c_d), ("skin", _c_d),
-                ("mode", _c_i32), ("reserved", _c_i32)]
+                ("mode", _c_i32), ("damping", _c_i32), ("rs6", _c_d), ("rs8", _c_d),
+                ("s9", _c_d), ("r_atm", _c_d)]
 
 
 class d3_table(ctypes.Structure):
@@ -151,8 +157,11 @@ def _stream(stream):
 # ------------------------------------------------------------ raw calls --
 
 def make_params(s6=1.0, a1=0.4289, s8=0.7875, a2=4.4407, r_pot=12.0, r_cn=6.0,
-                skin=0.0, mode=D3_MODE_PLAIN_F64):
-    return d3_params(s6, a1, s8, a2, r_pot, r_cn, skin, int(mode), 0)
+                skin=0.0, mode=D3_MODE_PLAIN_F64, damping=D3_DAMP_BJ, rs6=1.217, rs8=1.0,
+                s9=0.0, r_atm=None):
+    return d3_params(s6, a1, s8, a2, r_pot, r_cn, skin, int(mode),
+                     int(DAMPINGS.get(damping, damping)), rs6, rs8, s9,
+                     r_cn if r_atm is None else r_atm)
 
 
 class _Table:
@@ -257,7 +266,7 @@ def d3_list_stats(ctx):
             "mean_cn": out[3], "bins": out[4], "images": out[5]}
 
 
-PHASES = ("sort", "update", "cn", "pair", "chain", "list")
+PHASES = ("sort", "update", "cn", "pair", "chain", "list", "atm")
 
 
 def d3_set_timing(ctx, enable):

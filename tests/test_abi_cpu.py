@@ -43,7 +43,10 @@ def _create(**kw):
 
 @pytest.mark.parametrize("kw", [dict(r_pot=-1.0), dict(r_cn=0.0), dict(skin=-0.1),
                                 dict(r_pot=float("nan")), dict(mode=7),
-                                dict(a1=float("inf"))])
+                                dict(a1=float("inf")), dict(damping=2),
+                                dict(damping=1, rs6=0.0), dict(damping=1, rs8=-1.0),
+                                dict(s9=float("nan")), dict(s9=1.0, r_atm=6.5),
+                                dict(s9=1.0, r_atm=0.0)])
 def test_create_rejects_bad_params(kw):
     rc, out = _create(**kw)
     assert rc == d3.D3_ERR_INVALID_ARG

@@ -1,0 +1,138 @@
+"""GPU parity of the D3 variants the paper sets aside (Sec. II A, before
+Eq. 1) and that are built here as the D3 reference the paper cites defines
+them: zero damping of the two-body term and the three-body
+(Axilrod-Teller-Muto) term, alone and together, in the plain, precision
+and literal forms, through the C ABI, against the FP64 oracles.
+
+Gates as for Eq. 2: plain and literal |dE|/atom <= 1e-6 eV, max |dF| <=
+1e-5 eV/A, virial to 1e-9 relative; precision form max |dF| <= 1e-4 eV/A
+(energy and virial errors printed)."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import d3_oracle as O
+from oracle import d3_ref as R
+
+pytestmark = pytest.mark.gpu
+
+TAB = synth.make_table()
+ZERO = dict(damping="zero", s6=1.0, s8=0.722, rs6=1.217, rs8=1.0)
+VARIANTS = {"zero": dict(ZERO), "atm": dict(s9=1.0), "zero_atm": dict(ZERO, s9=1.0)}
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    return torch
+
+
+def _gpu(s, mode="plain", atom_virial=False, **prm):
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    calc = d3.D3(TAB, mode=mode, **prm)
+    calc.build(s["pos"], s["types"], s["cell"], s["pbc"])
+    out = calc.compute(atom_virial=atom_virial)
+    torch.cuda.synchronize()
+    calc.status()
+    res = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    res["energy"] = float(res["energy"][0])
+    calc.close()
+    return res
+
+
+def _check(got, ref, n, mode, label):
+    de = abs(got["energy"] - ref["energy"]) / n
+    df = np.abs(got["forces"] - ref["forces"]).max()
+    du = np.abs(got["atom_energy"] - ref["atom_energy"]).max()
+    wsc = np.abs(ref["virial"]).max()
+    dw = np.abs(got["virial"] - ref["virial"]).max()
+    print("%s %s: |dE|/atom=%.2e max|dF|=%.2e max|dU_i|=%.2e max|dW|=%.2e (rel %.2e)"
+          % (label, mode, de, df, du, dw, dw / wsc), flush=True)
+    assert de <= 1e-6 and du <= 1e-6
+    if mode == "prec":
+        assert df <= 1e-4 and dw <= 1e-6 * wsc
+    else:
+        assert df <= 1e-5 and dw <= 1e-9 * wsc
+
+
+def _small_cell(seed):
+    rng = np.random.default_rng(300 + seed)
+    cell = np.diag(rng.uniform(7.0, 11.0, 3))
+    cell[1, 0] = rng.uniform(-2, 2)
+    cell[2, :2] = rng.uniform(-2, 2, 2)
+    n = int(rng.integers(6, 40))
+    pbc = [(1, 1, 1), (1, 1, 0), (1, 0, 1), (1, 1, 1)][seed % 4]
+    return {"pos": rng.uniform(-0.1, 1.1, (n, 3)) @ cell,
+            "types": rng.integers(0, 5, n).astype(np.int32), "cell": cell, "pbc": np.array(pbc)}
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+@pytest.mark.parametrize("mode", ["plain", "prec", "literal"])
+def test_variants_small_cells(variant, mode):
+    """Small skewed cells (images within every cutoff, open axes, atoms
+    beyond the faces) with R_pot 10 A, R_cn = r_atm 5 A."""
+    kw = dict(VARIANTS[variant], r_pot=10.0, r_cn=5.0, r_atm=5.0)
+    for seed in range(4):
+        s = _small_cell(seed)
+        ref = O.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB, O.Params(**kw))
+        got = _gpu(s, mode=mode, **kw)
+        _check(got, ref, s["pos"].shape[0], mode, "%s seed %d" % (variant, seed))
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_variants_bilayer(variant):
+    """The 144-atom bilayer at the workload's cutoffs (12 / 6 A, r_atm 6 A)."""
+    g = synth.bilayer_graphene()
+    kw = dict(VARIANTS[variant], r_pot=12.0, r_cn=6.0, r_atm=6.0)
+    ref = O.d3(g["pos"], g["types"], g["cell"], g["pbc"], TAB, O.Params(**kw))
+    _check(_gpu(g, **kw), ref, 144, "plain", "bilayer " + variant)
+
+
+@pytest.mark.parametrize("variant,mode", [("zero", "plain"), ("atm", "plain"),
+                                          ("zero_atm", "plain"), ("zero", "prec"),
+                                          ("atm", "prec"), ("zero_atm", "prec")])
+def test_variants_mof_24000(variant, mode):
+    """The 24 000-atom MOF-like cell at 12 / 6 A (r_atm 6 A) against the C
+    oracle's cell-list evaluation of the whole cell."""
+    m = synth.mof_like(24000)
+    kw = dict(VARIANTS[variant], r_pot=12.0, r_cn=6.0, r_atm=6.0)
+    print("mof 24000", variant, mode, flush=True)
+    ref = R.d3(m["pos"], m["types"], m["cell"], m["pbc"], TAB, cells=True, **kw)
+    _check(_gpu(m, mode=mode, **kw), ref, 24000, mode, "mof24000 " + variant)
+
+
+def test_atm_per_atom_virial():
+    """Per-atom virials with the three-body term (a third of each
+    triangle's virial per vertex) against the oracle, and their sum rule."""
+    s = synth.mof_like(600, seed=17)
+    kw = dict(s9=1.0, r_pot=12.0, r_cn=6.0, r_atm=6.0)
+    ref = O.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB, O.Params(**kw))
+    got = _gpu(s, atom_virial=True, **kw)
+    sc = np.abs(ref["atom_virial"]).max()
+    dv = np.abs(got["atom_virial"] - ref["atom_virial"]).max()
+    print("atm per-atom virial: max|dW_i| = %.2e (rel %.2e)" % (dv, dv / sc), flush=True)
+    assert dv <= 1e-9 * sc
+    assert np.abs(got["atom_virial"].sum(0) - got["virial"]).max() <= 1e-9 * np.abs(got["virial"]).max()
+
+
+def test_variant_argument_checks():
+    """The surrogate pass implements Becke-Johnson damping only: zero
+    damping in that mode is refused at evaluation; a three-body cutoff
+    beyond R_cn is refused at creation."""
+    _torch()
+    from paper_2310_05279_amd import d3
+    with pytest.raises(d3.D3Error) as ei:
+        d3.D3(TAB, s9=1.0, r_cn=6.0, r_atm=7.0)
+    assert ei.value.code == d3.D3_ERR_INVALID_ARG
+    calc = d3.D3(TAB, mode="surrogate", **ZERO)
+    d3.d3_c6_surrogate_init(calc.ctx, 1)
+    w = d3.d3_c6_surrogate_get_weights(calc.ctx)
+    d3.d3_c6_surrogate_set_weights(calc.ctx, w)
+    g = synth.bilayer_graphene()
+    calc.build(g["pos"], g["types"], g["cell"], g["pbc"])
+    with pytest.raises(d3.D3Error) as ei:
+        calc.compute()
+    assert ei.value.code == d3.D3_ERR_INVALID_ARG
+    calc.close()
