@@ -399,11 +399,15 @@ int d3_c6_surrogate_adam_step(d3_ctx *ctx, int64_t m, const int32_t *pair,
  * the lists when an atom moved more than skin/2.  thermo: host double
  * array of (n_steps/every + 1) * 3 values (potential, kinetic, total
  * energy, eV) recorded every `every` steps from step 0, or NULL.
- * rebuilds: host int64[1] or NULL.  A build must precede the first call.
- * Synchronises.  Errors: STATE, INVALID_ARG, HIP; CAPACITY if a rebuild
- * could not fit the lists; after the run, SPECIES or INVALID_ARG if the
- * device recorded a bad species index or a non-finite position during it
- * (the run then went on with contained values and its results are not
+ * rebuilds: host int64[1] or NULL, the number of list builds made.  A build
+ * must precede the first call.  The decision to rebuild is taken on the
+ * device each step (no host synchronisation); the stream is synchronised
+ * every 16 steps, at thermo records and at the end, and a list overflow
+ * found there sends the run back to the state saved at the previous such
+ * point, with grown lists.  Errors: STATE, INVALID_ARG, HIP; CAPACITY if
+ * the lists overflowed repeatedly; after the run, SPECIES or INVALID_ARG if
+ * the device recorded a bad species index or a non-finite position during
+ * it (the run then went on with contained values and its results are not
  * meaningful). */
 int d3_md_nve(d3_ctx *ctx, int64_t n_steps, double dt, double *pos,
               double *vel, const double *mass, int32_t every, double *thermo,

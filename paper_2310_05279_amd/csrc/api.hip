@@ -432,12 +432,16 @@ int list_stats(d3_ctx* c, hipStream_t s, int* mc)
 // size_lists the list lengths are counted first and the capacities set
 // (one synchronisation).
 int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists,
-              hipStream_t s)
+              hipStream_t s, const int* need)
 {
     const int n = (int)c->n;
     const Geo& g = c->geo;
     int* count = c->count.as<int>();
     int* fill = count + g.nbins;
+    // a build decided on the device (need) reuses the sizes and relies on
+    // the counts that every completed build leaves at zero
+    if (need && (size_lists || !c->counts_clean))
+        return fail(D3_ERR_STATE, "a device-decided rebuild needs a completed sized build");
     // the bin counts and scatter cursors are left at zero by the ranking
     // kernel of the previous build; they are cleared here only after an
     // allocation or a build that did not complete
@@ -445,13 +449,14 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
     if (!c->counts_clean) HIPCHK(hipMemsetAsync(count, 0, 2 * (size_t)g.nbins * sizeof(int), s));
     c->counts_clean = false;
     launch_bin(n, pos, type, c->n_elem, g, c->bin_of.as<int>(), c->shift.as<double4>(), count,
-               c->type_copy.as<int32_t>(), c->status.as<int>(), s);
-    launch_scan(g.nbins, count, c->bin_start.as<int>(), c->scan_tmp.as<int>(), s);
-    launch_scatter(n, c->bin_of.as<int>(), c->bin_start.as<int>(), fill, c->perm_tmp.as<int>(), s);
+               c->type_copy.as<int32_t>(), c->status.as<int>(), s, need);
+    launch_scan(g.nbins, count, c->bin_start.as<int>(), c->scan_tmp.as<int>(), s, need);
+    launch_scatter(n, c->bin_of.as<int>(), c->bin_start.as<int>(), fill, c->perm_tmp.as<int>(), s,
+                   need);
     launch_rank(n, c->perm_tmp.as<int>(), c->bin_of.as<int>(), c->bin_start.as<int>(), pos,
                 c->type_copy.as<int32_t>(), c->shift.as<double4>(), c->perm.as<int>(),
                 c->pos_s.as<double4>(), c->shift_s.as<double4>(), c->ref_s.as<double4>(),
-                g.nbins, c->slab.as<int>(), count, s);
+                g.nbins, c->slab.as<int>(), count, s, need);
     HIPCHK(hipGetLastError());
     const double rp = c->prm.r_pot + c->prm.skin, rcn = c->prm.r_cn + c->prm.skin;
     if (size_lists) {
@@ -463,8 +468,8 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
         int mc[8];
         D3CHK(list_stats(c, s, mc));
         // headroom for later rebuilds of the same geometry (MD)
-        c->cap_p = std::max(1, mc[0] + std::max(16, mc[0] / 8));
-        c->cap_c = std::max(1, mc[1] + std::max(16, mc[1] / 8));
+        c->cap_p = std::max(std::max(1, mc[0] + std::max(16, mc[0] / 8)), c->min_cap_p);
+        c->cap_c = std::max(std::max(1, mc[1] + std::max(16, mc[1] / 8)), c->min_cap_c);
         c->cap_p = (c->cap_p + 3) & ~3;
         c->cap_c = (c->cap_c + 3) & ~3;
         const size_t N = (size_t)(n > 0 ? n : 1);
@@ -476,7 +481,8 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
     launch_list(n, c->pos_s.as<double4>(), c->bin_start.as<int>(), c->slab.as<int>(), g,
                 c->row_tab.as<RowSpan>(), c->img_tab.as<double4>(),
                 rp * rp, rcn * rcn, c->list_p.as<uint32_t>(), c->cnt_p.as<int>(), c->cap_p,
-                c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, 0, c->status.as<int>(), s);
+                c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c, 0, c->status.as<int>(), s,
+                need);
     phase_mark(c, PH_LIST, s);
     HIPCHK(hipGetLastError());
     c->counts_clean = true;
@@ -543,7 +549,7 @@ int update_positions(d3_ctx* c, const double* pos, hipStream_t s)
     phase_mark(c, PH_UPDATE, s);
     launch_update((int)c->n, pos, c->perm.as<int>(), c->shift_s.as<double4>(),
                   c->ref_s.as<double4>(), c->pos_s.as<double4>(), hs * hs,
-                  c->status.as<int>(), s);
+                  c->status.as<int>(), c->status.as<int>(), ST_STALE, s);
     phase_mark(c, PH_UPDATE, s);
     HIPCHK(hipGetLastError());
     return D3_OK;

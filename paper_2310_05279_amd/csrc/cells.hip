@@ -29,10 +29,11 @@ static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 __global__ void __launch_bounds__(BLOCK)
 k_bin(int n, const double* __restrict__ pos, const int32_t* __restrict__ type,
       int n_elem, Geo g, int* __restrict__ bin_of, double4* __restrict__ shift,
-      int* __restrict__ count, int32_t* __restrict__ type_copy, int* __restrict__ status)
+      int* __restrict__ count, int32_t* __restrict__ type_copy, int* __restrict__ status,
+      const int* __restrict__ need)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (need && *need == 0)) return;
     double r[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
     int t = type[i];
     if (t < 0 || t >= n_elem) {
@@ -93,8 +94,10 @@ __device__ int block_excl_scan(int v, int* sh, int* total)
 constexpr int SCAN_ONE_MAX = 65536;
 
 __global__ void __launch_bounds__(1024)
-k_scan_one(int m, const int* __restrict__ count, int* __restrict__ out)
+k_scan_one(int m, const int* __restrict__ count, int* __restrict__ out,
+           const int* __restrict__ need)
 {
+    if (need && *need == 0) return;
     __shared__ int wsum[2][1024 / WAVE];
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     int carry = 0;
@@ -145,8 +148,10 @@ k_scan_one(int m, const int* __restrict__ count, int* __restrict__ out)
 constexpr int SCAN_PER_BLOCK = 1024;
 
 __global__ void __launch_bounds__(BLOCK)
-k_scan_local(int m, const int* __restrict__ in, int* __restrict__ out, int* __restrict__ blocksum)
+k_scan_local(int m, const int* __restrict__ in, int* __restrict__ out, int* __restrict__ blocksum,
+             const int* __restrict__ need)
 {
+    if (need && *need == 0) return;
     __shared__ int sh[BLOCK];
     int base = blockIdx.x * SCAN_PER_BLOCK + threadIdx.x * 4;
     int v[4], s = 0;
@@ -166,8 +171,10 @@ k_scan_local(int m, const int* __restrict__ in, int* __restrict__ out, int* __re
 }
 
 __global__ void __launch_bounds__(1024)
-k_scan_top(int nblocks, int* __restrict__ blocksum, int* __restrict__ total)
+k_scan_top(int nblocks, int* __restrict__ blocksum, int* __restrict__ total,
+           const int* __restrict__ need)
 {
+    if (need && *need == 0) return;
     __shared__ int sh[1024];
     int carry = 0;
     for (int c = 0; c < nblocks; c += 1024) {
@@ -183,8 +190,9 @@ k_scan_top(int nblocks, int* __restrict__ blocksum, int* __restrict__ total)
 
 __global__ void __launch_bounds__(BLOCK)
 k_scan_add(int m, int* __restrict__ out, const int* __restrict__ blocksum,
-           const int* __restrict__ total)
+           const int* __restrict__ total, const int* __restrict__ need)
 {
+    if (need && *need == 0) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < m) out[i] += blocksum[i / SCAN_PER_BLOCK];
     if (i == 0) out[m] = *total;
@@ -192,10 +200,10 @@ k_scan_add(int m, int* __restrict__ out, const int* __restrict__ blocksum,
 
 __global__ void __launch_bounds__(BLOCK)
 k_scatter(int n, const int* __restrict__ bin_of, const int* __restrict__ bin_start,
-          int* __restrict__ fill, int* __restrict__ perm_tmp)
+          int* __restrict__ fill, int* __restrict__ perm_tmp, const int* __restrict__ need)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (need && *need == 0)) return;
     int b = bin_of[i];
     int slot = bin_start[b] + atomicAdd(&fill[b], 1);
     perm_tmp[slot] = i;
@@ -209,10 +217,11 @@ k_rank(int n, const int* __restrict__ perm_tmp, const int* __restrict__ bin_of,
        const int* __restrict__ bin_start, const double* __restrict__ pos,
        const int32_t* __restrict__ type_copy, const double4* __restrict__ shift,
        int* __restrict__ perm, double4* __restrict__ pos_s, double4* __restrict__ shift_s,
-       double4* __restrict__ ref_s, int nbins, int* __restrict__ slab, int* __restrict__ count)
+       double4* __restrict__ ref_s, int nbins, int* __restrict__ slab, int* __restrict__ count,
+       const int* __restrict__ need)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    if (k >= n || (need && *need == 0)) return;
     const int v = perm_tmp[k];
     const int b = bin_of[v];
     const int s = bin_start[b], e = bin_start[b + 1];
@@ -255,7 +264,8 @@ __device__ __forceinline__ bool dead_atom(const double4& p) { return __double2hi
 __global__ void __launch_bounds__(BLOCK)
 k_update(int n, const double* __restrict__ pos, const int* __restrict__ perm,
          const double4* __restrict__ shift_s, const double4* __restrict__ ref_s,
-         double4* __restrict__ pos_s, double half_skin2, int* __restrict__ status)
+         double4* __restrict__ pos_s, double half_skin2, int* __restrict__ status,
+         int* __restrict__ stale_out, int stale_bit)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -273,7 +283,7 @@ k_update(int n, const double* __restrict__ pos, const int* __restrict__ perm,
     double4 r = ref_s[k];
     double dx = x - r.x, dy = y - r.y, dz = z - r.z;
     double d2 = dx * dx + dy * dy + dz * dz;
-    if (!(d2 <= half_skin2)) atomicOr(status, ST_STALE);
+    if (!(d2 <= half_skin2)) atomicOr(stale_out, stale_bit);
     pos_s[k] = make_double4(x, y, z, p.w);
 }
 
@@ -318,8 +328,9 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
        const double4* __restrict__ img_tab, double rp2, double rc2,
        uint32_t* __restrict__ list_p, int* __restrict__ cnt_p, int cap_p,
        uint32_t* __restrict__ list_c, int* __restrict__ cnt_c, int cap_c,
-       int* __restrict__ status)
+       int* __restrict__ status, const int* __restrict__ need)
 {
+    if (need && *need == 0) return;  // the same for every thread of the grid
     __shared__ double4 s_img[IMG ? IMG_LDS : 1];
     __shared__ RowSpan s_rows[TABLE ? ROW_LDS : 1];
     load_images<IMG>(s_img, img_tab, g.n_img);
@@ -536,67 +547,68 @@ k_cnt_stats(int n, const int* __restrict__ cnt_p, const int* __restrict__ cnt_c,
 
 void launch_bin(int n, const double* pos, const int32_t* type, int n_elem,
                 const Geo& g, int* bin_of, double4* shift, int* count,
-                int32_t* type_copy, int* status, hipStream_t s)
+                int32_t* type_copy, int* status, hipStream_t s, const int* need)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_bin, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s, n, pos,
-                       type, n_elem, g, bin_of, shift, count, type_copy, status);
+                       type, n_elem, g, bin_of, shift, count, type_copy, status, need);
 }
 
-void launch_scan(int nbins, const int* count, int* bin_start, int* tmp, hipStream_t s)
+void launch_scan(int nbins, const int* count, int* bin_start, int* tmp, hipStream_t s,
+                 const int* need)
 {
     if (nbins <= SCAN_ONE_MAX) {
-        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, s, nbins, count, bin_start);
+        hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, s, nbins, count, bin_start, need);
         return;
     }
     int nb = nblk(nbins, SCAN_PER_BLOCK);
     hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(BLOCK), 0, s, nbins, count,
-                       bin_start, tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, nb, tmp, tmp + nb);
+                       bin_start, tmp, need);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, nb, tmp, tmp + nb, need);
     hipLaunchKernelGGL(k_scan_add, dim3(nblk(nbins, BLOCK)), dim3(BLOCK), 0, s,
-                       nbins, bin_start, tmp, tmp + nb);
+                       nbins, bin_start, tmp, tmp + nb, need);
 }
 
 void launch_scatter(int n, const int* bin_of, const int* bin_start, int* fill,
-                    int* perm_tmp, hipStream_t s)
+                    int* perm_tmp, hipStream_t s, const int* need)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_scatter, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s, n,
-                       bin_of, bin_start, fill, perm_tmp);
+                       bin_of, bin_start, fill, perm_tmp, need);
 }
 
 void launch_rank(int n, const int* perm_tmp, const int* bin_of, const int* bin_start,
                  const double* pos, const int32_t* type_copy, const double4* shift,
                  int* perm, double4* pos_s, double4* shift_s, double4* ref_s, int nbins,
-                 int* slab, int* count, hipStream_t s)
+                 int* slab, int* count, hipStream_t s, const int* need)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_rank, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s, n, perm_tmp,
                        bin_of, bin_start, pos, type_copy, shift, perm, pos_s, shift_s,
-                       ref_s, nbins, slab, count);
+                       ref_s, nbins, slab, count, need);
 }
 
 void launch_update(int n, const double* pos, const int* perm,
                    const double4* shift_s, const double4* ref_s,
                    double4* pos_s, double half_skin2, int* status,
-                   hipStream_t s)
+                   int* stale_out, int stale_bit, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_update, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s, n,
-                       pos, perm, shift_s, ref_s, pos_s, half_skin2, status);
+                       pos, perm, shift_s, ref_s, pos_s, half_skin2, status, stale_out, stale_bit);
 }
 
 void launch_list(int n, const double4* pos_s, const int* bin_start, const int* slab, const Geo& g,
                  const RowSpan* row_tab, const double4* img_tab, double rp2, double rc2,
                  uint32_t* list_p, int* cnt_p, int cap_p, uint32_t* list_c, int* cnt_c,
-                 int cap_c, int count_only, int* status, hipStream_t s)
+                 int cap_c, int count_only, int* status, hipStream_t s, const int* need)
 {
     if (n <= 0) return;
 #define D3_LIST(I, C, T)                                                                       \
     hipLaunchKernelGGL((k_list<I, C, T>),                                                      \
                        dim3(pass_blocks((const void*)&k_list<I, C, T>, g.nbins)), dim3(BLOCK), \
                        0, s, pos_s, bin_start, slab, g, row_tab, img_tab, rp2, rc2, list_p,    \
-                       cnt_p, cap_p, list_c, cnt_c, cap_c, status)
+                       cnt_p, cap_p, list_c, cnt_c, cap_c, status, need)
     const bool lds = g.n_img <= IMG_LDS;
     // the row table (trimmed, R_cn rows first) only for deep stencils
     if (g.nrows > 0) {

@@ -74,6 +74,9 @@ struct d3_ctx {
     // a build overflowed its lists (seen in the status word): the lists are
     // truncated until a build sizes them again
     bool lists_bad = false;
+    // smallest list capacities a sizing build may choose (raised after an
+    // overflow seen during MD, from the counts that overflowed)
+    int min_cap_p = 0, min_cap_c = 0;
     // host staging of the image translations and stencil row table of a
     // build: growable vectors, or fixed arrays (stage_fixed) given by the
     // allocation-free entry point
@@ -127,12 +130,17 @@ int check_build_args(int64_t n, const double* pos, const int32_t* type, const do
 int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const double* cell,
           const int32_t* pbc, hipStream_t s);
 int rebuild_grow(d3_ctx* c, const double* pos, hipStream_t s);
+// binning, sort and lists on stream s (size_lists: count first and size the
+// lists, one synchronisation); need: a device flag gating the whole build
+int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists, hipStream_t s,
+              const int* need = nullptr);
 int update_positions(d3_ctx* c, const double* pos, hipStream_t s);
 int coordination(d3_ctx* c, int mode, hipStream_t s);
 int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial,
              double* atom_energy, double* atom_virial, const double* vel, double* heat_current,
              int acc, hipStream_t s);
 int read_status(d3_ctx* c, hipStream_t s, int* out);
+int list_stats(d3_ctx* c, hipStream_t s, int* mc);  // max/sum of the last build's list lengths
 int status_code(int bits);
 int alloc_proj(d3_ctx* c, int mode);
 

@@ -83,26 +83,32 @@ struct PairScal {
 };
 
 // ---- launchers (cells.hip) --------------------------------------------
+// The build kernels take `need`: NULL, or a device flag read first by every
+// thread, the whole kernel doing nothing while it is 0 (a rebuild decided
+// on the device, with no host synchronisation).
 void launch_bin(int n, const double* pos, const int32_t* type, int n_elem,
                 const Geo& g, int* bin_of, double4* shift, int* count,
-                int32_t* type_copy, int* status, hipStream_t s);
-void launch_scan(int nbins, const int* count, int* bin_start, int* tmp, hipStream_t s);
+                int32_t* type_copy, int* status, hipStream_t s, const int* need = nullptr);
+void launch_scan(int nbins, const int* count, int* bin_start, int* tmp, hipStream_t s,
+                 const int* need = nullptr);
 void launch_scatter(int n, const int* bin_of, const int* bin_start, int* fill,
-                    int* perm_tmp, hipStream_t s);
+                    int* perm_tmp, hipStream_t s, const int* need = nullptr);
 void launch_rank(int n, const int* perm_tmp, const int* bin_of, const int* bin_start,
                  const double* pos, const int32_t* type_copy, const double4* shift,
                  int* perm, double4* pos_s, double4* shift_s, double4* ref_s, int nbins,
-                 int* slab, int* count, hipStream_t s);
+                 int* slab, int* count, hipStream_t s, const int* need = nullptr);
 void launch_list(int n, const double4* pos_s, const int* bin_start, const int* slab, const Geo& g,
                  const RowSpan* row_tab,
                  const double4* img_tab, double rp2, double rc2, uint32_t* list_p,
                  int* cnt_p, int cap_p, uint32_t* list_c, int* cnt_c, int cap_c,
-                 int count_only, int* status, hipStream_t s);
+                 int count_only, int* status, hipStream_t s, const int* need = nullptr);
 void launch_cnt_stats(int n, const int* cnt_p, const int* cnt_c, int* out, hipStream_t s);
+// copies the caller's positions into the sorted layout; an atom that moved
+// more than half the skin ORs stale_bit into *stale_out
 void launch_update(int n, const double* pos, const int* perm,
                    const double4* shift_s, const double4* ref_s,
                    double4* pos_s, double half_skin2, int* status,
-                   hipStream_t s);
+                   int* stale_out, int stale_bit, hipStream_t s);
 
 // ---- launchers (cn.hip, disp.hip, chain.hip) --------------------------
 // Workgroups of BLOCK threads for a pass whose waves take `units` work

@@ -442,3 +442,37 @@ def test_md_nve_matches_oracle_integrator():
     assert thermo[:, 0] == pytest.approx(rth[::5, 0], rel=1e-9)
     assert thermo[:, 1] == pytest.approx(rth[::5, 1], rel=1e-9)
     calc.close()
+
+
+def test_md_list_overflow_restarts_and_matches_oracle():
+    """A contracting cell: every atom's velocity points at the centre, so
+    the density rises until a device-decided rebuild overflows the lists
+    sized at the start.  The MD driver sees the overflow at its next check,
+    goes back to its last restart point, grows the lists and replays the
+    steps: the trajectory matches the oracle-driven integrator as if nothing
+    had happened."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    m = synth.mof_like(600, density=0.02, seed=44)
+    mid = 0.5 * m["cell"].sum(axis=0)
+    vel = -0.012 * (m["pos"] - mid)  # A/fs: the cell shrinks towards its centre
+    mass = np.asarray(synth.MASSES_AMU)[m["types"]]
+    calc = d3.D3(TAB, skin=1.0)
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    cap0 = calc.stats()["max_pot"]
+    p = torch.as_tensor(m["pos"], device="cuda").clone()
+    v = torch.as_tensor(vel, device="cuda").clone()
+    ms = torch.as_tensor(mass, device="cuda")
+    n_steps = 30
+    thermo, rebuilds = d3.d3_md_nve(calc.ctx, n_steps, 1.0, p, v, ms, every=5)
+    st = calc.stats()
+    rp, rv, rth = md_oracle.run(m["pos"], vel, mass, m["types"], m["cell"], m["pbc"], TAB,
+                                n_steps, 1.0)
+    dp = np.abs(p.cpu().numpy() - rp).max()
+    dv = np.abs(v.cpu().numpy() - rv).max()
+    print("contracting md: list max %d -> %d, builds %d, max|dx|=%.2e max|dv|=%.2e"
+          % (cap0, st["max_pot"], rebuilds, dp, dv), flush=True)
+    assert st["max_pot"] > 1.2 * cap0  # the lists really had to grow
+    assert dp < 1e-9 and dv < 1e-10
+    assert thermo[:, 0] == pytest.approx(rth[::5, 0], rel=1e-9)
+    calc.close()
