@@ -436,8 +436,9 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
 {
     const int n = (int)c->n;
     const Geo& g = c->geo;
+    // counts and scatter cursors of nbins + 1 bins (the last: atoms left out)
     int* count = c->count.as<int>();
-    int* fill = count + g.nbins;
+    int* fill = count + g.nbins + 1;
     // a build decided on the device (need) reuses the sizes and relies on
     // the counts that every completed build leaves at zero
     if (need && (size_lists || !c->counts_clean))
@@ -446,17 +447,19 @@ int run_build(d3_ctx* c, const double* pos, const int32_t* type, bool size_lists
     // kernel of the previous build; they are cleared here only after an
     // allocation or a build that did not complete
     phase_mark(c, PH_BUILD, s);
-    if (!c->counts_clean) HIPCHK(hipMemsetAsync(count, 0, 2 * (size_t)g.nbins * sizeof(int), s));
+    if (!c->counts_clean)
+        HIPCHK(hipMemsetAsync(count, 0, 2 * ((size_t)g.nbins + 1) * sizeof(int), s));
     c->counts_clean = false;
     launch_bin(n, pos, type, c->n_elem, g, c->bin_of.as<int>(), c->shift.as<double4>(), count,
                c->type_copy.as<int32_t>(), c->status.as<int>(), s, need);
-    launch_scan(g.nbins, count, c->bin_start.as<int>(), c->scan_tmp.as<int>(), s, need);
+    launch_scan(g.nbins + 1, count, c->bin_start.as<int>(), c->scan_tmp.as<int>(), s, need);
     launch_scatter(n, c->bin_of.as<int>(), c->bin_start.as<int>(), fill, c->perm_tmp.as<int>(), s,
                    need);
     launch_rank(n, c->perm_tmp.as<int>(), c->bin_of.as<int>(), c->bin_start.as<int>(), pos,
                 c->type_copy.as<int32_t>(), c->shift.as<double4>(), c->perm.as<int>(),
                 c->pos_s.as<double4>(), c->shift_s.as<double4>(), c->ref_s.as<double4>(),
-                g.nbins, c->slab.as<int>(), count, s, need);
+                g.nbins, c->slab.as<int>(), count, c->cnt_p.as<int>(), c->cnt_c.as<int>(), s,
+                need);
     HIPCHK(hipGetLastError());
     const double rp = c->prm.r_pot + c->prm.skin, rcn = c->prm.r_cn + c->prm.skin;
     if (size_lists) {
@@ -521,11 +524,11 @@ int build(d3_ctx* c, int64_t n, const double* pos, const int32_t* type, const do
         c->geo = g;
         std::memcpy(c->cell, cell, sizeof(c->cell));
         D3CHK(alloc_atoms(c, n));
-        D3CHK(ensure(c->count, 2 * (size_t)g.nbins * sizeof(int)));
+        D3CHK(ensure(c->count, 2 * ((size_t)g.nbins + 1) * sizeof(int)));
         c->counts_clean = false;
-        D3CHK(ensure(c->bin_start, ((size_t)g.nbins + 1) * sizeof(int)));
+        D3CHK(ensure(c->bin_start, ((size_t)g.nbins + 2) * sizeof(int)));
         D3CHK(ensure(c->slab, 16 * sizeof(int)));
-        D3CHK(ensure(c->scan_tmp, ((size_t)g.nbins / 1024 + 4) * sizeof(int)));
+        D3CHK(ensure(c->scan_tmp, ((size_t)g.nbins / 1024 + 5) * sizeof(int)));
         D3CHK(ensure(c->img_tab, (size_t)g.n_img * sizeof(double4)));
         HIPCHK(hipMemcpyAsync(c->img_tab.p, c->h_img, (size_t)g.n_img * sizeof(double4),
                               hipMemcpyHostToDevice, s));

@@ -63,8 +63,13 @@ k_bin(int n, const double* __restrict__ pos, const int32_t* __restrict__ type,
         // distances only shrink, so the stencil still covers every pair
         b[k] = !(q >= 0.0) ? 0 : (q >= (double)(g.nb[k] - 1) ? g.nb[k] - 1 : (int)q);
     }
-    if (!finite) atomicOr(status, ST_NONFINITE);
+    // an atom with a non-finite position goes to the extra bin nbins, which
+    // no stencil visits and no list wave takes: it is left out of every list
     int bin = (b[2] * g.nb[1] + b[1]) * g.nb[0] + b[0];
+    if (!finite) {
+        atomicOr(status, ST_NONFINITE);
+        bin = g.nbins;
+    }
     bin_of[i] = bin;
     shift[i] = make_double4(sh[0], sh[1], sh[2], 0.0);
     atomicAdd(&count[bin], 1);
@@ -218,7 +223,7 @@ k_rank(int n, const int* __restrict__ perm_tmp, const int* __restrict__ bin_of,
        const int32_t* __restrict__ type_copy, const double4* __restrict__ shift,
        int* __restrict__ perm, double4* __restrict__ pos_s, double4* __restrict__ shift_s,
        double4* __restrict__ ref_s, int nbins, int* __restrict__ slab, int* __restrict__ count,
-       const int* __restrict__ need)
+       int* __restrict__ cnt_p, int* __restrict__ cnt_c, const int* __restrict__ need)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n || (need && *need == 0)) return;
@@ -229,9 +234,10 @@ k_rank(int n, const int* __restrict__ perm_tmp, const int* __restrict__ bin_of,
     for (int q = s; q < e; q++) rank += (perm_tmp[q] < v) ? 1 : 0;
     const int o = s + rank;
     // the bin's count and scatter cursor are spent: leave them at zero for
-    // the next build (every atom of the bin writes the same zeros)
+    // the next build (every atom of the bin writes the same zeros); the
+    // counts are nbins + 1 long, the last for atoms left out of the lists
     count[b] = 0;
-    count[nbins + b] = 0;
+    count[nbins + 1 + b] = 0;
     // XCD slabs of bins holding equal shares of the sorted atoms: slab x
     // starts at the bin of sorted atom floor(n x / 8)
 #pragma unroll
@@ -241,16 +247,18 @@ k_rank(int n, const int* __restrict__ perm_tmp, const int* __restrict__ bin_of,
     const double4 sh = shift[v];
     const double x = pos[3 * v] + sh.x, y = pos[3 * v + 1] + sh.y, z = pos[3 * v + 2] + sh.z;
     perm[o] = v;
-    // an atom whose position is not finite (the binning kernel reported it)
-    // is left out of every list: it gets a finite stand-in position and a
-    // mark in the high word of w, which the list kernel reads, so that no
-    // pass ever sees a non-finite coordinate
-    if (isfinite(x) && isfinite(y) && isfinite(z)) {
+    // an atom whose position is not finite (binned into the extra bin, after
+    // every other atom) gets empty lists, a finite stand-in position (so that
+    // no pass ever reads a non-finite coordinate) and a mark in the high word
+    // of w, which the per-evaluation position copy reads
+    if (b < nbins) {
         pos_s[o] = make_double4(x, y, z, __hiloint2double(0, type_copy[v]));
         ref_s[o] = make_double4(x, y, z, 0.0);
     } else {
         pos_s[o] = make_double4(0.0, 0.0, 0.0, __hiloint2double(1, type_copy[v]));
         ref_s[o] = make_double4(0.0, 0.0, 0.0, 0.0);
+        cnt_p[o] = 0;
+        cnt_c[o] = 0;
     }
     shift_s[o] = sh;
 }
@@ -451,7 +459,7 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
                     bool valid[LIST_AHEAD];
 #pragma unroll
                     for (int u = 0; u < LIST_AHEAD; u++) {
-                        valid[u] = kb + u * WAVE + lane < total && !dead_atom(pp[u]);
+                        valid[u] = kb + u * WAVE + lane < total;
                         const double4 T = image<IMG>(s_img, img_tab, (uint32_t)ii[u]);
                         qx[u] = pp[u].x + T.x;
                         qy[u] = pp[u].y + T.y;
@@ -463,7 +471,6 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
                     for (int t = 0; t < na; t++) {
                         const int a = a0 + t;
                         const double4 pa = pos_s[a];
-                        const bool alive = !dead_atom(pa);  // wave-uniform
                         const uint32_t self = ((uint32_t)a << g.img_bits) | img_self;
                         int np_t = __builtin_amdgcn_readlane(np, t);
                         int nc_t = __builtin_amdgcn_readlane(nc, t);
@@ -474,7 +481,7 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
                             if (u >= nch) break;
                             const double dx = qx[u] - pa.x, dy = qy[u] - pa.y, dz = qz[u] - pa.z;
                             const double r2 = dx * dx + dy * dy + dz * dz;
-                            const bool other = alive & valid[u] & (code[u] != self);
+                            const bool other = valid[u] & (code[u] != self);
                             const bool inp = other & (r2 < rp2w);
                             const bool inc =
                                 (!TABLE || kb + u * WAVE < cn_total) & other & (r2 < rc2w);
@@ -580,12 +587,12 @@ void launch_scatter(int n, const int* bin_of, const int* bin_start, int* fill,
 void launch_rank(int n, const int* perm_tmp, const int* bin_of, const int* bin_start,
                  const double* pos, const int32_t* type_copy, const double4* shift,
                  int* perm, double4* pos_s, double4* shift_s, double4* ref_s, int nbins,
-                 int* slab, int* count, hipStream_t s, const int* need)
+                 int* slab, int* count, int* cnt_p, int* cnt_c, hipStream_t s, const int* need)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_rank, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s, n, perm_tmp,
                        bin_of, bin_start, pos, type_copy, shift, perm, pos_s, shift_s,
-                       ref_s, nbins, slab, count, need);
+                       ref_s, nbins, slab, count, cnt_p, cnt_c, need);
 }
 
 void launch_update(int n, const double* pos, const int* perm,

@@ -93,10 +93,13 @@ void launch_scan(int nbins, const int* count, int* bin_start, int* tmp, hipStrea
                  const int* need = nullptr);
 void launch_scatter(int n, const int* bin_of, const int* bin_start, int* fill,
                     int* perm_tmp, hipStream_t s, const int* need = nullptr);
+// nbins: the bins of the geometry; bin nbins holds the atoms left out of the
+// lists (non-finite positions), whose list counts k_rank sets to zero
 void launch_rank(int n, const int* perm_tmp, const int* bin_of, const int* bin_start,
                  const double* pos, const int32_t* type_copy, const double4* shift,
                  int* perm, double4* pos_s, double4* shift_s, double4* ref_s, int nbins,
-                 int* slab, int* count, hipStream_t s, const int* need = nullptr);
+                 int* slab, int* count, int* cnt_p, int* cnt_c, hipStream_t s,
+                 const int* need = nullptr);
 void launch_list(int n, const double4* pos_s, const int* bin_start, const int* slab, const Geo& g,
                  const RowSpan* row_tab,
                  const double4* img_tab, double rp2, double rc2, uint32_t* list_p,

@@ -152,9 +152,9 @@ extern "C" int d3_energy_forces_virial_noalloc(const d3_params* prm, const d3_ta
               cv.take(c.Pf, N * NPIECEF * 4 * sizeof(float)) &&
               cv.take(c.vpart, nparts) && cv.take(c.vpart2, nparts) &&
               cv.take(c.vpart3, nparts) &&
-              cv.take(c.count, 2 * (size_t)NA_MAX_BINS * sizeof(int)) &&
-              cv.take(c.bin_start, ((size_t)NA_MAX_BINS + 1) * sizeof(int)) &&
-              cv.take(c.scan_tmp, ((size_t)NA_MAX_BINS / 1024 + 4) * sizeof(int)) &&
+              cv.take(c.count, 2 * ((size_t)NA_MAX_BINS + 1) * sizeof(int)) &&
+              cv.take(c.bin_start, ((size_t)NA_MAX_BINS + 2) * sizeof(int)) &&
+              cv.take(c.scan_tmp, ((size_t)NA_MAX_BINS / 1024 + 5) * sizeof(int)) &&
               cv.take(c.slab, 16 * sizeof(int)) &&
               cv.take(c.img_tab, (size_t)NA_MAX_IMG * sizeof(double4)) &&
               cv.take(c.row_tab, (size_t)NA_MAX_ROWS * sizeof(RowSpan));
