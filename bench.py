@@ -245,7 +245,7 @@ def main():
                     help="skip the precision/surrogate/other-cell/MD fields")
     ap.add_argument("--no-flops", action="store_true",
                     help="skip the unique-pair count (roofline fields become null)")
-    ap.add_argument("--sur-epochs", type=int, default=300)
+    ap.add_argument("--sur-epochs", type=int, default=3000)
     ap.add_argument("--md-steps", type=int, default=200)
     ap.add_argument("--graph", action="store_true",
                     help="also time the headline step replayed from a HIP graph")
@@ -407,7 +407,7 @@ def main():
         d3mod.d3_c6_surrogate_init(run.calc.ctx, 5)
         t0 = time.perf_counter()
         loss = d3mod.d3_c6_surrogate_train(run.calc.ctx, n_samples=1_000_000,
-                                           epochs=args.sur_epochs, lr=5e-3, lr_final=1e-6,
+                                           epochs=args.sur_epochs, lr=1e-2, lr_final=1e-6,
                                            seed=4, cn_hi=cn_hi)
         t_train = time.perf_counter() - t0
         weights = d3mod.d3_c6_surrogate_get_weights(run.calc.ctx)

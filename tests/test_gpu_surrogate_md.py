@@ -209,7 +209,8 @@ def _cn_hi(system):
 @pytest.fixture(scope="module")
 def trained():
     """Surrogate trained on 10^6 samples (config of the 200 000-atom cell:
-    CN box from the 99.9th CN percentile of a MOF-like cell + 0.5)."""
+    CN box from the 99.9th CN percentile of a MOF-like cell + 0.5), 3 000
+    epochs of Adam with a cosine step size from 1e-2 (about 30 s)."""
     _torch()
     from paper_2310_05279_amd import d3
     m = synth.mof_like(3000, seed=31)
@@ -219,7 +220,7 @@ def trained():
     ei, ej, ni, nj = _queries(20000, 77, cn_hi)
     exact = _exact(calc, ei, ej, ni, nj)
     before = _sur(calc, ei, ej, ni, nj, 1)
-    loss = d3.d3_c6_surrogate_train(calc.ctx, n_samples=1_000_000, epochs=300, lr=5e-3,
+    loss = d3.d3_c6_surrogate_train(calc.ctx, n_samples=1_000_000, epochs=3000, lr=1e-2,
                                     lr_final=1e-6, seed=4, cn_hi=cn_hi)
     after = _sur(calc, ei, ej, ni, nj, 1)
     w = d3.d3_c6_surrogate_get_weights(calc.ctx)
@@ -237,9 +238,9 @@ def test_training_gain(trained):
     ea = np.sqrt(np.mean((a - ex) ** 2, axis=0)) / scale
     print("final training loss %.3e; relative RMS error before %s after %s"
           % (trained["loss"], eb, ea), flush=True)
-    # every head improves several-fold; C6 itself to about a percent of its range
-    assert np.all(ea < eb / 3.0)
-    assert ea[0] < 1.5e-2
+    # every head improves by more than 20x; C6 itself to a few 1e-3 of its range
+    assert np.all(ea < eb / 20.0)
+    assert ea[0] < 3e-3
 
 
 SUR_GATE = 1e-4  # eV/A, force max-abs against the exact FP64 oracle
@@ -247,7 +248,8 @@ SUR_GATE = 1e-4  # eV/A, force max-abs against the exact FP64 oracle
 
 @pytest.mark.xfail(strict=True, reason=(
     "surrogate force gate (1e-4 eV/A against the exact FP64 oracle) not met: max|dF| "
-    "3.0e-2 eV/A on the 3 000-atom cell and 4.7e-2 eV/A on the 200 000-atom cell as measured"))
+    "4.0e-3 eV/A on the 3 000-atom cell and 1.2e-3 eV/A on sampled atoms of the 200 000-atom "
+    "cell as measured after 3 000 training epochs"))
 def test_surrogate_forces_against_oracle(trained):
     """Energy, forces and virial with the surrogate C6 against the exact
     FP64 oracle (Eq. 3 itself, no network): every atom of a 3 000-atom
