@@ -182,6 +182,16 @@ int d3_build_neighbors(d3_ctx *ctx, int64_t n, const double *pos,
                        const int32_t *type, const double *cell,
                        const int32_t *pbc, void *stream);
 
+/* The positions the current neighbour lists were built from, exactly as
+ * the caller passed them (unwrapped), in the caller's atom order.
+ * pos_out: device (n,3) FP64.  A build from these positions gives the same
+ * bins, sorted order and lists, so an MD checkpoint that keeps them next to
+ * the positions and velocities resumes bit for bit: build from them with
+ * d3_build_neighbors, then continue with d3_md_nve (whose stale test
+ * measures displacements from them).  Asynchronous.  Errors: STATE (no
+ * build), INVALID_ARG, HIP. */
+int d3_build_positions(d3_ctx *ctx, double *pos_out, void *stream);
+
 /* Coordination numbers, Eq. 4, for positions pos (device (n,3), same
  * atoms as the last build).  Keeps n_i in the context; if cn_out (device
  * double[n]) is not NULL, writes them there in the caller's atom order.

@@ -775,6 +775,18 @@ int d3_coordination(d3_ctx* c, const double* pos, double* cn_out, void* stream)
     return D3_OK;
 }
 
+int d3_build_positions(d3_ctx* c, double* pos_out, void* stream)
+{
+    if (!c) return fail(D3_ERR_INVALID_ARG, "ctx is NULL");
+    if (!c->built) return fail(D3_ERR_STATE, "d3_build_positions before d3_build_neighbors");
+    if (c->n > 0 && !pos_out) return fail(D3_ERR_INVALID_ARG, "pos_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    launch_build_pos((int)c->n, c->perm.as<int>(), c->ref_s.as<double4>(), pos_out, s);
+    HIPCHK(hipGetLastError());
+    return D3_OK;
+}
+
 static int run_evaluate(d3_ctx* c, const double* pos, const d3_outputs& o, uint32_t flags,
                         void* stream, const char* who)
 {

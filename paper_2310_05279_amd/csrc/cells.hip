@@ -251,12 +251,14 @@ k_rank(int n, const int* __restrict__ perm_tmp, const int* __restrict__ bin_of,
     // every other atom) gets empty lists, a finite stand-in position (so that
     // no pass ever reads a non-finite coordinate) and a mark in the high word
     // of w, which the per-evaluation position copy reads
+    // ref_s keeps the caller's positions of this build, unwrapped and
+    // exact: the stale test measures displacements from them, and a
+    // checkpoint reads them back to rebuild the same lists
+    ref_s[o] = make_double4(pos[3 * v], pos[3 * v + 1], pos[3 * v + 2], 0.0);
     if (b < nbins) {
         pos_s[o] = make_double4(x, y, z, __hiloint2double(0, type_copy[v]));
-        ref_s[o] = make_double4(x, y, z, 0.0);
     } else {
         pos_s[o] = make_double4(0.0, 0.0, 0.0, __hiloint2double(1, type_copy[v]));
-        ref_s[o] = make_double4(0.0, 0.0, 0.0, 0.0);
         cnt_p[o] = 0;
         cnt_c[o] = 0;
     }
@@ -288,8 +290,8 @@ k_update(int n, const double* __restrict__ pos, const int* __restrict__ perm,
         return;
     }
     if (dead_atom(p)) return;
-    double4 r = ref_s[k];
-    double dx = x - r.x, dy = y - r.y, dz = z - r.z;
+    const double4 r = ref_s[k];
+    const double dx = pos[3 * i] - r.x, dy = pos[3 * i + 1] - r.y, dz = pos[3 * i + 2] - r.z;
     double d2 = dx * dx + dy * dy + dz * dz;
     if (!(d2 <= half_skin2)) atomicOr(stale_out, stale_bit);
     pos_s[k] = make_double4(x, y, z, p.w);
@@ -603,6 +605,26 @@ void launch_update(int n, const double* pos, const int* perm,
     if (n <= 0) return;
     hipLaunchKernelGGL(k_update, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s, n,
                        pos, perm, shift_s, ref_s, pos_s, half_skin2, status, stale_out, stale_bit);
+}
+
+// The caller's positions of the last build, back in the caller's order.
+__global__ void __launch_bounds__(BLOCK)
+k_build_pos(int n, const int* __restrict__ perm, const double4* __restrict__ ref_s,
+            double* __restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int i = perm[k];
+    const double4 r = ref_s[k];
+    out[3 * i] = r.x;
+    out[3 * i + 1] = r.y;
+    out[3 * i + 2] = r.z;
+}
+
+void launch_build_pos(int n, const int* perm, const double4* ref_s, double* out, hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_build_pos, dim3(nblk(n, BLOCK)), dim3(BLOCK), 0, s, n, perm, ref_s, out);
 }
 
 void launch_list(int n, const double4* pos_s, const int* bin_start, const int* slab, const Geo& g,

@@ -153,5 +153,6 @@ int launch_atm(int n, const double4* pos_s, const double4* img_tab, int n_img, i
                const double* wd, double* Fp, double* U, double* G, double* Vp, double* part,
                hipStream_t s);
 void launch_scatter_out(int n, const double* src, const int* perm, double* dst, hipStream_t s);
+void launch_build_pos(int n, const int* perm, const double4* ref_s, double* out, hipStream_t s);
 
 }  // namespace d3

@@ -90,6 +90,7 @@ _SIGS = {
     "d3_set_mode": (_c_i32, [_vp, _c_i32]),
     "d3_build_neighbors": (_c_i32, [_vp, _c_i64, _vp, _vp, _vp, _vp, _vp]),
     "d3_coordination": (_c_i32, [_vp, _vp, _vp, _vp]),
+    "d3_build_positions": (_c_i32, [_vp, _vp, _vp]),
     "d3_energy_forces_virial": (_c_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _c_u32, _vp]),
     "d3_evaluate": (_c_i32, [_vp, _vp, ctypes.POINTER(d3_outputs), _c_u32, _vp]),
     "d3_status": (_c_i32, [_vp]),
@@ -200,6 +201,10 @@ def d3_build_neighbors(ctx, pos, types, cell, pbc, stream=None):
     _check(lib().d3_build_neighbors(ctx, n, _ptr(pos), _ptr(types),
                                     cell.ctypes.data, pbc.ctypes.data,
                                     _stream(stream)))
+
+
+def d3_build_positions(ctx, pos_out, stream=None):
+    _check(lib().d3_build_positions(ctx, _ptr(pos_out), _stream(stream)))
 
 
 def d3_coordination(ctx, pos, cn_out=None, stream=None):
