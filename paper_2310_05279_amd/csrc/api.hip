@@ -1032,8 +1032,9 @@ int evaluate(d3_ctx* c, int mode, double* energy, double* forces, double* virial
         phase_mark(c, PH_ATM, s);
         n3 = launch_atm(n, c->pos_s.as<double4>(), c->img_tab.as<double4>(), g.n_img, g.img_bits,
                         c->list_c.as<uint32_t>(), c->cnt_c.as<int>(), c->cap_c,
-                        c->d_tab.as<ElemTab>(), c->d_c6.as<double>(), c->d_pc.as<double4>(),
-                        c->prm.s9, c->prm.r_atm * c->prm.r_atm, c->w.as<double>(),
+                        c->d_tab.as<ElemTab>(), c->n_elem, c->d_c6.as<double>(),
+                        c->d_pc.as<double4>(), c->prm.s9, c->prm.r_atm * c->prm.r_atm,
+                        c->w.as<double>(),
                         c->wd.as<double>(), c->Fp.as<double>(), c->U.as<double>(),
                         c->G.as<double>(), Vp, c->vpart3.as<double>(), s);
         phase_mark(c, PH_ATM, s);

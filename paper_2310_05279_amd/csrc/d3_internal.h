@@ -149,9 +149,9 @@ void launch_final(int na, const double* part_a, int nb, const double* part_b, in
                   hipStream_t s);
 int launch_atm(int n, const double4* pos_s, const double4* img_tab, int n_img, int img_bits,
                const uint32_t* list_c, const int* cnt_c, int cap_c, const ElemTab* tab,
-               const double* c6ref, const double4* pc, double s9, double ra2, const double* w,
-               const double* wd, double* Fp, double* U, double* G, double* Vp, double* part,
-               hipStream_t s);
+               int n_elem, const double* c6ref, const double4* pc, double s9, double ra2,
+               const double* w, const double* wd, double* Fp, double* U, double* G, double* Vp,
+               double* part, hipStream_t s);
 void launch_scatter_out(int n, const double* src, const int* perm, double* dst, hipStream_t s);
 void launch_build_pos(int n, const int* perm, const double4* ref_s, double* out, hipStream_t s);
 

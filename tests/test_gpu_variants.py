@@ -103,6 +103,18 @@ def test_variants_mof_24000(variant, mode):
     _check(_gpu(m, mode=mode, **kw), ref, 24000, mode, "mof24000 " + variant)
 
 
+@pytest.mark.parametrize("mode", ["plain", "prec"])
+def test_atm_long_lists(mode):
+    """The three-body term over R_cn lists several 64-entry blocks long
+    (R_cn 9.5 A with a 1 A skin: ~190 entries per atom, pairs within and
+    across blocks) and r_atm below R_cn (7.5 A), so that blocks also hold
+    entries beyond r_atm; against the C oracle."""
+    m = synth.mof_like(1500, seed=33)
+    kw = dict(s9=1.0, r_pot=12.0, r_cn=9.5, r_atm=7.5)
+    ref = R.d3(m["pos"], m["types"], m["cell"], m["pbc"], TAB, cells=True, **kw)
+    _check(_gpu(m, mode=mode, skin=1.0, **kw), ref, 1500, mode, "atm long lists")
+
+
 def test_atm_per_atom_virial():
     """Per-atom virials with the three-body term (a third of each
     triangle's virial per vertex) against the oracle, and their sum rule."""
