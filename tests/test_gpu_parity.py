@@ -560,6 +560,26 @@ def test_full_size_against_cell_list_oracle(case, mode):
         assert df <= 1e-4 and dcn <= 1e-5 and dw <= 1e-6 * wsc
 
 
+@pytest.mark.parametrize("mode", ["plain", "prec"])
+def test_two_bin_units_sparse_skewed_cell(mode):
+    """A large periodic bulk cell builds its lists in units of two
+    neighbouring bins (from 100 000 bins on): a sparse (0.004 A^-3) sheared
+    cell of 36 000 atoms with 47 x 47 x 48 bins (an odd count along the first
+    lattice vector, so every row ends in a single-bin unit) and a 1 A skin,
+    against the oracle's cell-list evaluation of the whole cell."""
+    m = synth.mof_like(36000, density=0.004, seed=77)
+    shear = np.array([[1.0, 0.0, 0.0], [0.12, 1.0, 0.0], [-0.08, 0.1, 1.0]])
+    s = {"pos": m["pos"] @ shear, "types": m["types"], "cell": m["cell"] @ shear,
+         "pbc": m["pbc"]}
+    ref = R.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB, cells=True)
+    gpu = run_gpu(s, mode=mode, skin=1.0)
+    assert gpu["stats"]["bins"] >= 100000
+    if mode == "plain":
+        compare(gpu, ref, 36000, label="two-bin units plain")
+    else:
+        compare(gpu, ref, 36000, tol_f=1e-4, tol_w_rel=1e-6, label="two-bin units prec")
+
+
 def test_capacity_overflow_reported_bounded_and_regrown():
     """List overflow: lists sized (with a 1 A skin) for a sparse cell
     overflow when its atoms are drawn together into the middle of the cell
