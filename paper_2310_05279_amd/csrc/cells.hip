@@ -298,8 +298,9 @@ k_update(int n, const double* __restrict__ pos, const int* __restrict__ perm,
 }
 
 constexpr int LIST_AHEAD = 4;  // candidate steps whose loads are in flight together
-constexpr int UNIT2_UNITE = 10;         // most atoms of a two-bin unit built together
-constexpr int UNIT2_MIN_BINS = 100000;  // two-bin units from this many bins on
+constexpr int UB_UNITE = 5;             // most atoms per bin of a unit built together
+constexpr int UNIT2_MIN_BINS = 100000;  // units of several bins from this many bins on
+constexpr int LIST_UB = 2;  // bins per unit then (three were no faster at 10^6 atoms)
 constexpr int ROW_LDS = 1024;  // stencil rows of the row table held in LDS
 
 // number of set bits of m below this lane
@@ -333,7 +334,7 @@ __device__ __forceinline__ int wave_incl_scan(int v)
 // with a ballot into the atom's row.  The test is the same FP64 arithmetic
 // as the passes, with a 1e-12 relative widening so that no pair a pass would
 // accept is missed; the passes make the exact decision.  COUNT: count only.
-template <bool IMG, bool COUNT, bool TABLE, bool UNIT2>
+template <bool IMG, bool COUNT, bool TABLE, int UB>
 __global__ void __launch_bounds__(BLOCK)
 k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
        const int* __restrict__ slab, Geo g, const RowSpan* __restrict__ row_tab,
@@ -356,39 +357,40 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
     const int n1r = 2 * g.reach[1] + 1, n2r = 2 * g.reach[2] + 1;
     const int nrows = TABLE ? g.nrows : n1r * n2r;
     const uint32_t img_self = (uint32_t)((g.timg[0] * n1 + g.timg[1]) * n2 + g.timg[2]);
-    // the waves of XCD x take the units of slab x round-robin.  A unit is one
-    // bin, or (UNIT2) two neighbouring bins along the first lattice vector,
-    // bins 2k and 2k + 1 of a row: their stencils differ by one bin per row,
-    // so the candidate set-up of the union serves the atoms of both.  A unit
-    // whose two bins hold more than UNIT2_UNITE atoms takes them one at a time
+    // the waves of XCD x take the units of slab x round-robin.  A unit is UB
+    // neighbouring bins along the first lattice vector, bins UB k .. UB k +
+    // UB - 1 of a row: their stencils differ by one bin per row and bin, so
+    // the candidate set-up of the union serves the atoms of all of them.  A
+    // unit holding more than UB_UNITE atoms per bin takes its bins one at a
+    // time
     const int per = gridDim.x >> 3;
     const int lb = xcd_block();
     const int x = lb / per;
     const int wave0 = (lb - x * per) * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
-    const int hu = UNIT2 ? (nb0 + 1) / 2 : nb0;  // units per row
+    const int hu = (nb0 + UB - 1) / UB;  // units per row
     // the first unit whose first bin is at or after bin b
     auto unit_of = [&](int b) -> int {
-        if constexpr (!UNIT2) return b;
+        if constexpr (UB == 1) return b;
         const int r = b / nb0, c0 = b - r * nb0;
-        return r * hu + (c0 + 1) / 2;
+        return r * hu + (c0 + UB - 1) / UB;
     };
     const int u_lo = unit_of(__builtin_amdgcn_readfirstlane(slab[x]));
     const int u_hi = unit_of(__builtin_amdgcn_readfirstlane(slab[x + 1]));
     for (int un = __builtin_amdgcn_readfirstlane(u_lo + wave0); un < u_hi;
          un += per * WAVES_PER_BLOCK) {
         int bin0 = un, nbh = 1;
-        if constexpr (UNIT2) {
-            const int r = un / hu, k2 = 2 * (un - r * hu);
-            bin0 = r * nb0 + k2;
-            nbh = k2 + 1 < nb0 ? 2 : 1;
+        if constexpr (UB > 1) {
+            const int r = un / hu, k0 = UB * (un - r * hu);
+            bin0 = r * nb0 + k0;
+            nbh = min(UB, nb0 - k0);
         }
         const int s_all = __builtin_amdgcn_readfirstlane(bin_start[bin0]);
         const int e_all = __builtin_amdgcn_readfirstlane(bin_start[bin0 + nbh]);
         if (s_all == e_all) continue;
-        const bool unite = nbh == 2 && e_all - s_all <= UNIT2_UNITE;
-        const int nsub = nbh == 2 && !unite ? 2 : 1;
+        const bool unite = e_all - s_all <= UB_UNITE * nbh;
+        const int nsub = unite ? 1 : nbh;
       for (int sub = 0; sub < nsub; sub++) {
-        const int bin = bin0 + sub, span = unite ? 2 : 1;
+        const int bin = bin0 + sub, span = unite ? nbh : 1;
         const int s = __builtin_amdgcn_readfirstlane(bin_start[bin]);
         const int e = __builtin_amdgcn_readfirstlane(bin_start[bin + span]);
         if (s == e) continue;
@@ -674,30 +676,30 @@ void launch_list(int n, const double4* pos_s, const int* bin_start, const int* s
     // atoms, were measured slower with them
     const bool unit2 = g.nrows == 0 && g.nbins >= UNIT2_MIN_BINS && g.pbc[0] && g.pbc[1] &&
                        g.pbc[2];
-    const int units = unit2 ? g.nbins / g.nb[0] * ((g.nb[0] + 1) / 2) : g.nbins;
+    const int units = unit2 ? g.nbins / g.nb[0] * ((g.nb[0] + LIST_UB - 1) / LIST_UB) : g.nbins;
     if (g.nrows > 0) {
         if (count_only) {
-            if (lds) D3_LIST(true, true, true, false);
-            else D3_LIST(false, true, true, false);
+            if (lds) D3_LIST(true, true, true, 1);
+            else D3_LIST(false, true, true, 1);
         } else {
-            if (lds) D3_LIST(true, false, true, false);
-            else D3_LIST(false, false, true, false);
+            if (lds) D3_LIST(true, false, true, 1);
+            else D3_LIST(false, false, true, 1);
         }
     } else if (unit2) {
         if (count_only) {
-            if (lds) D3_LIST(true, true, false, true);
-            else D3_LIST(false, true, false, true);
+            if (lds) D3_LIST(true, true, false, LIST_UB);
+            else D3_LIST(false, true, false, LIST_UB);
         } else {
-            if (lds) D3_LIST(true, false, false, true);
-            else D3_LIST(false, false, false, true);
+            if (lds) D3_LIST(true, false, false, LIST_UB);
+            else D3_LIST(false, false, false, LIST_UB);
         }
     } else {
         if (count_only) {
-            if (lds) D3_LIST(true, true, false, false);
-            else D3_LIST(false, true, false, false);
+            if (lds) D3_LIST(true, true, false, 1);
+            else D3_LIST(false, true, false, 1);
         } else {
-            if (lds) D3_LIST(true, false, false, false);
-            else D3_LIST(false, false, false, false);
+            if (lds) D3_LIST(true, false, false, 1);
+            else D3_LIST(false, false, false, 1);
         }
     }
 #undef D3_LIST
