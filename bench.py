@@ -340,7 +340,7 @@ def main():
         cpu = {"value": n / dt, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
                "sample": "one full FP64 E+F+W evaluation of the same 10^6-atom cell by the C "
                          "oracle's cell-list mode on %d OpenMP threads (%.1f s)" % (threads, dt),
-               "cpu_model": cpu_model(),
+               "cpu_model": cpu_model(), "host_threads": len(os.sched_getaffinity(0)),
                "single_thread": {"value": m1 / dt1, "unit": "atom-steps/s", "cores": 1,
                                  "sample": "the CN, dispersion and chain passes of %d of the "
                                            "cell's atoms, one thread (%.1f s)" % (m1, dt1)}}
