@@ -20,9 +20,9 @@ def _torch():
     return torch
 
 
-def _context_result(s, mode):
+def _context_result(s, mode, **kw):
     from paper_2310_05279_amd import d3
-    calc = d3.D3(TAB, mode=mode)
+    calc = d3.D3(TAB, mode=mode, **kw)
     calc.build(s["pos"], s["types"], s["cell"], s["pbc"])
     out = calc.compute()
     _torch().cuda.synchronize()
@@ -32,7 +32,7 @@ def _context_result(s, mode):
     return res
 
 
-def _noalloc_result(s, mode):
+def _noalloc_result(s, mode, **kw):
     torch = _torch()
     from paper_2310_05279_amd import d3
     n = s["pos"].shape[0]
@@ -43,7 +43,7 @@ def _noalloc_result(s, mode):
            "forces": torch.full((n, 3), 7.0, dtype=torch.float64, device=dev),
            "virial": torch.full((3, 3), 7.0, dtype=torch.float64, device=dev),
            "atom_energy": torch.full((n,), 7.0, dtype=torch.float64, device=dev)}
-    prm = d3.make_params(mode=d3.MODES[mode])
+    prm = d3.make_params(mode=d3.MODES[mode], **kw)
     d3.d3_energy_forces_virial_noalloc(prm, TAB, pos, types, s["cell"], s["pbc"],
                                        out["energy"], out["forces"], out["virial"],
                                        out["atom_energy"])
@@ -69,6 +69,23 @@ def test_noalloc_matches_the_context_path_twice(mode):
     n = small["pos"].shape[0]
     assert abs(got["energy"][0] - ref["energy"]) / n <= 1e-6
     assert np.abs(got["forces"] - ref["forces"]).max() <= (1e-5 if mode == "plain" else 1e-4)
+
+
+def test_noalloc_with_zero_damping_and_three_body_term():
+    """The variants (zero damping and the three-body term, whose pass has its
+    own partial sums in the static array) bit for bit what the context path
+    gives, and within the plain gates of the oracle."""
+    from paper_2310_05279_amd import d3
+    s = synth.mof_like(1500, seed=32)
+    kw = dict(damping=d3.D3_DAMP_ZERO, s8=0.722, rs6=1.217, rs8=1.0, s9=1.0)
+    want = _context_result(s, "plain", **kw)
+    got = _noalloc_result(s, "plain", **kw)
+    for k in want:
+        assert np.array_equal(got[k], want[k]), "%s differs" % k
+    ref = R.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB, damping="zero", s8=0.722,
+               rs6=1.217, rs8=1.0, s9=1.0)
+    assert abs(got["energy"][0] - ref["energy"]) / 1500 <= 1e-6
+    assert np.abs(got["forces"] - ref["forces"]).max() <= 1e-5
 
 
 def test_noalloc_limits_are_refused():
