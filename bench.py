@@ -37,6 +37,11 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
+# the D3 variants the paper sets aside, as options of the headline step
+_ZERO = dict(damping="zero", s6=1.0, s8=0.722, rs6=1.217, rs8=1.0)
+VARIANTS = {"bj": {}, "zero": _ZERO, "bj_atm": dict(s9=1.0, r_atm=6.0),
+            "zero_atm": dict(_ZERO, s9=1.0, r_atm=6.0)}
+
 # HBM bytes per launch of the dispersion pass on the 10^6-atom cell, from two
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch), each scaled by what the same counter read for a 512 MiB device
@@ -254,6 +259,9 @@ def main():
     ap.add_argument("--md-steps", type=int, default=200)
     ap.add_argument("--graph", action="store_true",
                     help="also time the headline step replayed from a HIP graph")
+    ap.add_argument("--variant", choices=sorted(VARIANTS), default="bj",
+                    help="the headline step with zero damping and/or the three-body term "
+                         "(for profiling those passes; no roofline or CPU baseline then)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run 3 plain device-to-device copies of this many MiB "
                          "(a known-size reference for HBM byte counters)")
@@ -278,9 +286,12 @@ def main():
     table = synth.make_table()
     system = synth.mof_like(1_000_000)
     n = system["pos"].shape[0]
-    log("workload mof_1M plain: warmup %d, steps %d" % (args.warmup, args.steps))
+    log("workload mof_1M plain %s: warmup %d, steps %d" % (args.variant, args.warmup, args.steps))
+    headline_kw = VARIANTS[args.variant]
+    if args.variant != "bj":
+        args.no_flops = args.no_cpu_baseline = True
 
-    run = Runner(system, table, "plain")
+    run = Runner(system, table, "plain", **headline_kw)
     ms = run.timed(args.steps, args.warmup)
     value = n / (ms * 1e-3)
     ms_graph = run.graphed(args.steps, args.warmup) if args.graph else None
@@ -435,9 +446,8 @@ def main():
         # the variants the paper sets aside: zero damping, the three-body term
         # (r_atm = R_cn = 6 A) and both, on the headline cell, plain FP64
         variants = {}
-        zero = dict(damping="zero", s6=1.0, s8=0.722, rs6=1.217, rs8=1.0)
-        for vname, kw in (("zero_damping", zero), ("bj_atm", dict(s9=1.0, r_atm=6.0)),
-                          ("zero_atm", dict(zero, s9=1.0, r_atm=6.0))):
+        for vname, kw in (("zero_damping", VARIANTS["zero"]), ("bj_atm", VARIANTS["bj_atm"]),
+                          ("zero_atm", VARIANTS["zero_atm"])):
             run = Runner(system, table, "plain", **kw)
             msv = run.timed(10, 2)
             phv = run.phases(5)
@@ -526,7 +536,9 @@ def main():
             "config": {"workload": "mof_like_1M (10^6 atoms, H,C,N,O,Zn 4:6:1:2:1, 0.04 "
                                    "atoms/A^3, seed 1000000; synthetic D3 table seed 2310; "
                                    "R_pot 12 A, R_cn 6 A; plain FP64; E+F+virial with the "
-                                   "neighbour build in every step)",
+                                   "neighbour build in every step)" +
+                                   ("" if args.variant == "bj" else
+                                    "; variant %s" % args.variant),
                        "n_atoms": n, "parallelism": "single GPU"},
             "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     print(json.dumps(line), flush=True)
