@@ -301,7 +301,10 @@ int d3_get_timing(d3_ctx *ctx, double *ms, int64_t *calls);
  *   energy, forces, virial, atom_energy: as for d3_energy_forces_virial
  *     (only energy is required);  flags: 0 or D3_ACCUMULATE.
  * The call synchronises the stream and returns the conditions the device
- * recorded (as d3_status would).  Errors: INVALID_ARG (n beyond the limit,
+ * recorded (as d3_status would).  Because it synchronises, and copies the
+ * converted table from host memory on every call, it is not itself meant
+ * to be recorded into a HIP graph: it serves code around a capture (or in
+ * a serving loop) that must not allocate.  Errors: INVALID_ARG (n beyond the limit,
  * surrogate mode, bad arguments), CAPACITY (more bins than 65536, more than
  * 1024 periodic images, or neighbour lists beyond the space left in the
  * array: about 7 million entries in all), CELL, SPECIES, HIP.  Calls on one
