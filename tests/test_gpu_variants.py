@@ -103,6 +103,18 @@ def test_variants_mof_24000(variant, mode):
     _check(_gpu(m, mode=mode, **kw), ref, 24000, mode, "mof24000 " + variant)
 
 
+def test_variants_full_size_mof1M():
+    """Zero damping and the three-body term together on the 10^6-atom cell in
+    the launch shape the bench times (lists in two-bin units, the three-body
+    pass over every atom), against the C oracle's cell-list evaluation of the
+    whole cell: every force and site energy, E and W, plain gates."""
+    m = synth.mof_like(1_000_000)
+    kw = dict(VARIANTS["zero_atm"], r_pot=12.0, r_cn=6.0, r_atm=6.0)
+    print("mof 10^6 zero+atm", flush=True)
+    ref = R.d3(m["pos"], m["types"], m["cell"], m["pbc"], TAB, cells=True, **kw)
+    _check(_gpu(m, **kw), ref, 1_000_000, "plain", "mof1M zero_atm")
+
+
 @pytest.mark.parametrize("mode", ["plain", "prec"])
 def test_atm_long_lists(mode):
     """The three-body term over R_cn lists several 64-entry blocks long
