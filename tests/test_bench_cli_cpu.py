@@ -35,7 +35,7 @@ def test_flops_per_pair_and_unique_pair_count():
     from oracle import d3_oracle as O
     assert bench._flops_per_pair(1, 1) == 66.0
     assert bench._flops_per_pair(5, 3) == 140.0
-    assert bench._flops_per_pair(3, 3) == 110.0  # the survey's K = 3 figure
+    assert bench._flops_per_pair(3, 3) == 110.0  # 56 + 36 + 18 at K_i = K_j = 3
     table = synth.make_table()
     m = synth.mof_like(1200, seed=19)  # a 31 A cube: one image per pair within 12 A
     flops, pairs = bench.algorithmic_pair_flops(m, table, 12.0)
