@@ -82,6 +82,31 @@ def test_variants_small_cells(variant, mode):
 
 
 @pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_variants_image_triangles_and_cluster(variant):
+    """Edge cases of the three-body term: a one-atom triclinic cell, whose
+    triangles are all made of the atom's own periodic images, a two-atom
+    cell, and a 40-atom cluster with no periodic axis."""
+    cell1 = np.array([[3.6, 0.0, 0.0], [0.9, 3.4, 0.0], [0.4, -0.6, 3.9]])
+    one = {"pos": np.array([[0.3, 0.2, 0.1]]), "types": np.array([4], np.int32), "cell": cell1,
+           "pbc": np.array([1, 1, 1])}
+    two = {"pos": np.array([[0.3, 0.2, 0.1], [1.9, 1.6, 2.2]]), "types": np.array([1, 3], np.int32),
+           "cell": cell1 * 1.3, "pbc": np.array([1, 1, 1])}
+    rng = np.random.default_rng(41)
+    pts = []
+    while len(pts) < 40:
+        p = rng.uniform(0, 9.0, 3)
+        if all(np.linalg.norm(p - q) > 1.2 for q in pts):
+            pts.append(p)
+    clu = {"pos": np.array(pts), "types": rng.integers(0, 5, 40).astype(np.int32),
+           "cell": np.eye(3) * 10.0, "pbc": np.array([0, 0, 0])}
+    kw = dict(VARIANTS[variant], r_pot=10.0, r_cn=6.0, r_atm=6.0)
+    for s, label in ((one, "one-atom cell"), (two, "two-atom cell"), (clu, "cluster")):
+        ref = O.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB, O.Params(**kw))
+        got = _gpu(s, **kw)
+        _check(got, ref, s["pos"].shape[0], "plain", "%s %s" % (variant, label))
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
 def test_variants_bilayer(variant):
     """The 144-atom bilayer at the workload's cutoffs (12 / 6 A, r_atm 6 A)."""
     g = synth.bilayer_graphene()
