@@ -39,6 +39,7 @@ namespace d3 {
 constexpr int ATM_M_LDS_ELEM = 8;  // C6 reference table in LDS up to 8 elements
 constexpr int ATM_BS = 32;          // raw list entries per block
 constexpr int ATM_SLOTS = 2 * ATM_BS;
+constexpr int ATM_Q = 128;          // queued triangles per wave (a ring)
 static_assert(ATM_BS <= WAVE, "one lane per raw entry of a block");
 constexpr double ATM_SR3 = 4.0 / 3.0;
 
@@ -191,6 +192,7 @@ k_atm(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_
     __shared__ double s_M[MLDS ? ATM_M_LDS_ELEM * ATM_M_LDS_ELEM * MAXREF * MAXREF : 1];
     __shared__ double s_u[WAVES_PER_BLOCK][2][MAXELEM * MAXREF];
     __shared__ AtmCache s_e[WAVES_PER_BLOCK];
+    __shared__ uint16_t s_q[WAVES_PER_BLOCK][ATM_Q];
     const int ne = tab->n_elem;
     load_images<IMG>(s_img, img_tab, n_img);
     // (R0^2)^(1/6) per element pair: R0c of a triangle is the product of three
@@ -278,34 +280,84 @@ k_atm(int n, const double4* __restrict__ pos_s, const double4* __restrict__ img_
             return (int)__popcll(m);
         };
         AtmAcc<AV> acc;
+        // Pairs of cached entries go through two steps: a cheap one that
+        // tests the third side and queues the pairs that close a triangle
+        // (about half of them) in this wave's LDS ring, and the full triangle
+        // evaluation, 64 queued pairs at a time.  Queued pairs name cache
+        // slots, so the queue is emptied before a block load overwrites any.
+        int qhead = 0, qn = 0;  // wave-uniform
+        auto run_batch = [&](int k) {
+            const uint32_t it = s_q[wv][(qhead + (lane < k ? lane : 0)) & (ATM_Q - 1)];
+            atm_pair<AV, MLDS>(ce, (int)(it & 0xFFu), (int)(it >> 8), lane < k, zi, ne, s_M,
+                               c6ref, s_r0c, s9, ra2, acc);
+            qhead = (qhead + k) & (ATM_Q - 1);
+            qn -= k;
+            __builtin_amdgcn_wave_barrier();
+        };
+        auto enqueue = [&](int e1, int e2, bool valid) {
+            const double bx = ce.dx[e2] - ce.dx[e1], by = ce.dy[e2] - ce.dy[e1],
+                         bz = ce.dz[e2] - ce.dz[e1];
+            const bool in = valid && bx * bx + by * by + bz * bz < ra2;
+            const unsigned long long m = __ballot(in);
+            if (in)
+                s_q[wv][(qhead + qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                          (uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))) &
+                        (ATM_Q - 1)] = (uint16_t)(e1 | (e2 << 8));
+            qn += (int)__popcll(m);
+            wave_lds_sync();
+            if (qn >= WAVE) run_batch(WAVE);
+        };
+        auto flush = [&]() {
+            if (qn > 0) run_batch(qn);
+        };
         const int nblk = (cnt + ATM_BS - 1) / ATM_BS;
-        for (int bi = 0; bi < nblk; bi++) {
-            const int mi = load_block(bi, 0);
-            // pairs inside block bi
-            const int ntri = mi * (mi - 1) / 2;
+        if (nblk <= 2) {
+            // both blocks stay in the cache: one triangle over all their entries
+            const int m0 = load_block(0, 0);
+            const int m1 = nblk == 2 ? load_block(1, ATM_BS) : 0;
+            const int m = m0 + m1;
+            const int ntri = m * (m - 1) / 2;
             for (int p0 = 0; p0 < ntri; p0 += WAVE) {
                 const int p = p0 + lane;
-                int e1 = 0, e2 = 1;
-                if (p < ntri) pair_of(p, e1, e2);
-                atm_pair<AV, MLDS>(ce, e1, e2, p < ntri, zi, ne, s_M, c6ref, s_r0c, s9, ra2,
-                                   acc);
+                int v1 = 0, v2 = 1;
+                if (p < ntri) pair_of(p, v1, v2);
+                const int e1 = v1 < m0 ? v1 : ATM_BS + (v1 - m0);
+                const int e2 = v2 < m0 ? v2 : ATM_BS + (v2 - m0);
+                enqueue(e1, e2, p < ntri);
             }
-            // pairs between block bi and every later block
-            for (int bj = bi + 1; bj < nblk && mi > 0; bj++) {
-                const int mj = load_block(bj, ATM_BS);
-                const int nrect = mi * mj;
-                const float inv = 1.0f / (float)(mj > 0 ? mj : 1);
-                for (int p0 = 0; p0 < nrect; p0 += WAVE) {
+            flush();
+        } else {
+            for (int bi = 0; bi < nblk; bi++) {
+                flush();
+                const int mi = load_block(bi, 0);
+                // pairs inside block bi
+                const int ntri = mi * (mi - 1) / 2;
+                for (int p0 = 0; p0 < ntri; p0 += WAVE) {
                     const int p = p0 + lane;
-                    int e1 = (int)((float)p * inv);
-                    if (e1 * mj > p) e1--;
-                    if ((e1 + 1) * mj <= p) e1++;
-                    const bool ok = p < nrect;
-                    e1 = ok ? e1 : 0;
-                    const int e2 = ok ? ATM_BS + (p - e1 * mj) : ATM_BS;
-                    atm_pair<AV, MLDS>(ce, e1, e2, ok, zi, ne, s_M, c6ref, s_r0c, s9, ra2, acc);
+                    int e1 = 0, e2 = 1;
+                    if (p < ntri) pair_of(p, e1, e2);
+                    enqueue(e1, e2, p < ntri);
+                }
+                // pairs between block bi and every later block
+                for (int bj = bi + 1; bj < nblk && mi > 0; bj++) {
+                    flush();
+                    const int mj = load_block(bj, ATM_BS);
+                    const int nrect = mi * mj;
+                    const float inv = 1.0f / (float)(mj > 0 ? mj : 1);
+                    for (int p0 = 0; p0 < nrect; p0 += WAVE) {
+                        const int p = p0 + lane;
+                        int e1 = (int)((float)p * inv);
+                        if (e1 * mj > p) e1--;
+                        if ((e1 + 1) * mj <= p) e1++;
+                        const bool ok = p < nrect;
+                        e1 = ok ? e1 : 0;
+                        const int e2 = ok ? ATM_BS + (p - e1 * mj) : ATM_BS;
+                        enqueue(e1, e2, ok);
+                    }
                 }
             }
+            flush();
         }
         double fx, fy, fz, ue, g;
         if constexpr (AV) {
