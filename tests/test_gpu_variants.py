@@ -152,6 +152,58 @@ def test_atm_long_lists(mode):
     _check(_gpu(m, mode=mode, skin=1.0, **kw), ref, 1500, mode, "atm long lists")
 
 
+@pytest.mark.parametrize("mode", ["plain", "literal"])
+def test_variants_twelve_elements(mode):
+    """Zero damping and the three-body term with a 12-element table, beyond
+    the eight elements whose C6 table the passes stage in LDS (the table is
+    read from global memory), against the C oracle."""
+    tab12 = synth.make_table(seed=77, n_elem=12)
+    m = synth.mof_like(900, seed=13)
+    types = np.random.default_rng(12).integers(0, 12, 900).astype(np.int32)
+    kw = dict(VARIANTS["zero_atm"], r_pot=12.0, r_cn=6.0, r_atm=6.0)
+    ref = R.d3(m["pos"], types, m["cell"], m["pbc"], tab12, **kw)
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    calc = d3.D3(tab12, mode=mode, **kw)
+    calc.build(m["pos"], types, m["cell"], m["pbc"])
+    out = calc.compute()
+    torch.cuda.synchronize()
+    calc.status()
+    got = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    got["energy"] = float(got["energy"][0])
+    calc.close()
+    _check(got, ref, 900, mode, "12 elements zero_atm")
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_variants_random_cells(seed):
+    """Both variants on random small cells: skewed lattice vectors of
+    5-14 A, any mix of periodic and open axes, 3-30 atoms (some outside the
+    cell), R_pot 5-20 A, R_cn from R_pot/4 to R_pot, r_atm from R_cn/2 to
+    R_cn (at most 8 A)."""
+    rng = np.random.default_rng(2000 + seed)
+    while True:
+        cell = np.diag(rng.uniform(5.0, 14.0, 3)) + rng.uniform(-2.5, 2.5, (3, 3)) * \
+            (1 - np.eye(3))
+        if abs(np.linalg.det(cell)) > 0.2 * np.prod(np.linalg.norm(cell, axis=1)):
+            break
+    pbc = rng.integers(0, 2, 3).astype(np.int32)
+    n = int(rng.integers(3, 31))
+    for _ in range(1000):
+        pos = rng.uniform(-0.3, 1.3, (n, 3)) @ cell
+        if O.entries(pos, cell, pbc, 0.9)[0].size == 0:
+            break
+    types = rng.integers(0, 5, n).astype(np.int32)
+    r_pot = float(rng.uniform(5.0, 20.0))
+    r_cn = float(rng.uniform(0.25, 1.0)) * r_pot
+    r_atm = min(float(rng.uniform(0.5, 1.0)) * r_cn, 8.0)
+    kw = dict(VARIANTS["zero_atm"], r_pot=r_pot, r_cn=r_cn, r_atm=r_atm)
+    s = {"pos": pos, "types": types, "cell": cell, "pbc": pbc}
+    ref = R.d3(pos, types, cell, pbc, TAB, **kw)
+    _check(_gpu(s, **kw), ref, n, "plain", "random cell %d (pbc %s, %d atoms, %.1f/%.1f/%.1f A)"
+           % (seed, pbc.tolist(), n, r_pot, r_cn, r_atm))
+
+
 def test_atm_per_atom_virial():
     """Per-atom virials with the three-body term (a third of each
     triangle's virial per vertex) against the oracle, and their sum rule."""
