@@ -277,6 +277,9 @@ def main():
     ap.add_argument("--variant", choices=sorted(VARIANTS), default="bj",
                     help="the headline step with zero damping and/or the three-body term "
                          "(for profiling those passes; no roofline or CPU baseline then)")
+    ap.add_argument("--form", choices=("plain", "prec"), default="plain",
+                    help="the headline step in the precision form (for profiling its passes; "
+                         "no roofline or CPU baseline then)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run 3 plain device-to-device copies of this many MiB "
                          "(a known-size reference for HBM byte counters)")
@@ -303,10 +306,10 @@ def main():
     n = system["pos"].shape[0]
     log("workload mof_1M plain %s: warmup %d, steps %d" % (args.variant, args.warmup, args.steps))
     headline_kw = VARIANTS[args.variant]
-    if args.variant != "bj":
+    if args.variant != "bj" or args.form != "plain":
         args.no_flops = args.no_cpu_baseline = True
 
-    run = Runner(system, table, "plain", **headline_kw)
+    run = Runner(system, table, args.form, **headline_kw)
     ms = run.timed(args.steps, args.warmup)
     value = n / (ms * 1e-3)
     ms_graph = run.graphed(args.steps, args.warmup) if args.graph else None
@@ -552,13 +555,15 @@ def main():
     line = {"metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f64", "data": "synthetic",
+            "dtype": "f64" if args.form == "plain" else "f32 (pair arithmetic; f64 sums)",
+            "data": "synthetic",
             "config": {"workload": "mof_like_1M (10^6 atoms, H,C,N,O,Zn 4:6:1:2:1, 0.04 "
                                    "atoms/A^3, seed 1000000; synthetic D3 table seed 2310; "
                                    "R_pot 12 A, R_cn 6 A; plain FP64; E+F+virial with the "
                                    "neighbour build in every step)" +
                                    ("" if args.variant == "bj" else
-                                    "; variant %s" % args.variant),
+                                    "; variant %s" % args.variant) +
+                                   ("" if args.form == "plain" else "; precision form"),
                        "n_atoms": n, "parallelism": "single GPU"},
             "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     print(json.dumps(line), flush=True)
