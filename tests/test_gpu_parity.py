@@ -530,8 +530,8 @@ def _full_case(case):
     return _FULL_REF[case]
 
 
-@pytest.mark.parametrize("case,mode", [("mof1M", "plain"), ("mof1M", "prec"),
-                                       ("graphene500k", "plain"), ("graphene500k", "prec")])
+@pytest.mark.parametrize("case,mode", [("graphene500k", "plain"), ("graphene500k", "prec"),
+                                       ("mof1M", "plain"), ("mof1M", "prec")])
 def test_full_size_against_cell_list_oracle(case, mode):
     """Full-size cells (the 10^6-atom MOF-like cube and the 500 000-atom
     bilayer) in the plain and precision forms, in the launch shape the bench
@@ -556,6 +556,59 @@ def test_full_size_against_cell_list_oracle(case, mode):
     assert de <= 1e-6 and du <= 1e-6
     if mode == "plain":
         assert df <= 1e-5 and dcn <= 1e-12 and dw <= 1e-9 * wsc
+    else:
+        assert df <= 1e-4 and dcn <= 1e-5 and dw <= 1e-6 * wsc
+
+
+@pytest.mark.parametrize("mode", ["plain", "prec"])
+def test_supercell_beyond_32_bit_list_offsets(mode):
+    """A 4 x 2 x 2 supercell of the 10^6-atom MOF-like cube (1.6e7 atoms,
+    lists at 13 A: ~5.9e9 entries, so list offsets and the summed lengths
+    pass 2^32) against the oracle's cell-list evaluation of the base cube:
+    periodicity fixes every copy of an atom to the base atom's force, site
+    energy and CN, and the energy and virial to 16 times the base cell's.
+    Every atom is checked, with the full-size gates of the plain and
+    precision forms.  The copies are replicas only up to rounding, which
+    bounds the plain form's CN check (see ``cn_tol``)."""
+    print("supercell", mode, flush=True)
+    s, ref = _full_case("mof1M")
+    n = s["pos"].shape[0]
+    reps = (4, 2, 2)
+    L = s["cell"]
+    shifts = [i * L[0] + j * L[1] + k * L[2]
+              for i in range(reps[0]) for j in range(reps[1]) for k in range(reps[2])]
+    sup = {"pos": np.concatenate([s["pos"] + t for t in shifts]),
+           "types": np.tile(s["types"], len(shifts)),
+           "cell": L * np.array(reps, dtype=np.float64)[:, None], "pbc": s["pbc"]}
+    m = len(shifts) * n
+    gpu = run_gpu(sup, mode=mode, skin=1.0)
+    st = gpu["stats"]
+    assert st["mean_pot"] * m > 2.0 ** 32 and st["max_pot"] * m > 2.0 ** 32
+    df = du = dcn = 0.0
+    for c in range(len(shifts)):
+        sl = slice(c * n, (c + 1) * n)
+        df = max(df, float(np.abs(gpu["forces"][sl] - ref["forces"]).max()))
+        du = max(du, float(np.abs(gpu["atom_energy"][sl] - ref["atom_energy"]).max()))
+        dcn = max(dcn, float(np.abs(gpu["cn"][sl] - ref["cn"]).max()))
+    de = abs(gpu["energy"] - len(shifts) * ref["energy"]) / m
+    wsc = len(shifts) * np.abs(ref["virial"]).max()
+    dw = np.abs(gpu["virial"] - len(shifts) * ref["virial"]).max()
+    print("supercell %s: %d atoms, %.3g entries: |dE|/atom=%.2e max|dF|=%.2e max|dU_i|=%.2e "
+          "max|dCN|=%.2e max|dW|=%.2e (rel %.2e)"
+          % (mode, m, st["mean_pot"] * m, de, df, du, dcn, dw, dw / wsc), flush=True)
+    # a tiled coordinate is rounded to half an ulp u of the largest magnitude
+    # (an image-shifted coordinate, below twice the longest cell edge), and so
+    # are the image shift and difference that form a displacement: each
+    # component may differ from the base cell's by 2u, a length by 2 sqrt(3) u.
+    # Eq. 4's counting function changes by at most 4 R_s / r^2 per Angstrom
+    # (R_s the largest covalent-radius sum, r >= the 1 A minimum separation)
+    u = float(np.spacing(2.0 * np.abs(sup["cell"]).sum(axis=1).max()))
+    slope = 4.0 * (2.0 * TAB["rcov"].max()) / 1.0 ** 2
+    cn_tol = st["max_cn"] * slope * 2.0 * np.sqrt(3.0) * u
+    print("CN bound from the tiling's rounding: %.2e" % cn_tol, flush=True)
+    assert de <= 1e-6 and du <= 1e-6
+    if mode == "plain":
+        assert df <= 1e-5 and dcn <= cn_tol and dw <= 1e-9 * wsc
     else:
         assert df <= 1e-4 and dcn <= 1e-5 and dw <= 1e-6 * wsc
 
