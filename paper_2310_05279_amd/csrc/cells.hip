@@ -515,8 +515,23 @@ k_list(const double4* __restrict__ pos_s, const int* __restrict__ bin_start,
                             const bool inp = other & (r2 < rp2w);
                             const bool inc =
                                 (!TABLE || kb + u * WAVE < cn_total) & other & (r2 < rc2w);
-                            const unsigned long long bp = __ballot(inp);
-                            const unsigned long long bc = __ballot(inc);
+                            unsigned long long bp, bc;
+                            if constexpr (TABLE) {
+                                bp = __ballot(inp);
+                                bc = __ballot(inc);
+                            } else {
+                                // a ballot of a combined predicate goes through a VGPR;
+                                // ballots of the single compares are the compares' own
+                                // lane masks, combined on the scalar unit (the valid
+                                // lanes are a prefix of the wave)
+                                const int nv = total - (kb + u * WAVE);
+                                const unsigned long long m_valid =
+                                    nv >= WAVE ? ~0ull : (1ull << (nv > 0 ? nv : 0)) - 1ull;
+                                const unsigned long long m_other =
+                                    m_valid & __builtin_amdgcn_ballot_w64(code[u] != self);
+                                bp = m_other & __builtin_amdgcn_ballot_w64(r2 < rp2w);
+                                bc = m_other & __builtin_amdgcn_ballot_w64(r2 < rc2w);
+                            }
                             if constexpr (!COUNT) {
                                 if (inp) {
                                     const int sp = np_t + lanes_below(bp);
