@@ -97,3 +97,28 @@ def test_error_message_is_per_call():
     L = d3.lib()
     L.d3_status(None)
     assert b"NULL" in L.d3_last_error()
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library every call raises at once: there is no
+    fallback path."""
+    monkeypatch.setattr(d3, "LIB_PATH", str(tmp_path / "libd3.so"))
+    monkeypatch.setattr(d3, "_lib", None)
+    with pytest.raises(OSError, match="not built"):
+        d3.lib()
+    with pytest.raises(OSError, match="not built"):
+        d3.D3(synth.make_table())
+
+
+def test_package_never_reaches_the_oracle():
+    """The product package names nothing under oracle/ (the oracle is test
+    infrastructure only), and its sources load no other shared library."""
+    pkg = os.path.join(ROOT, "paper_2310_05279_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if not f.endswith((".py", ".hip", ".h", ".cpp", ".c")):
+                continue
+            src = open(os.path.join(dirpath, f)).read()
+            assert not re.search(r"\boracle\b|d3ref", src), f
+            if f.endswith(".py"):
+                assert len(re.findall(r"ctypes\.CDLL\(", src)) <= 1, f
