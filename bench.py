@@ -277,8 +277,9 @@ def main():
     ap.add_argument("--variant", choices=sorted(VARIANTS), default="bj",
                     help="the headline step with zero damping and/or the three-body term "
                          "(for profiling those passes; no roofline or CPU baseline then)")
-    ap.add_argument("--form", choices=("plain", "prec"), default="plain",
-                    help="the headline step in the precision form (for profiling its passes; "
+    ap.add_argument("--form", choices=("plain", "prec", "sur"), default="plain",
+                    help="the headline step in the precision form, or with the surrogate C6 "
+                         "trained for --sur-epochs epochs first (for profiling their passes; "
                          "no roofline or CPU baseline then)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run 3 plain device-to-device copies of this many MiB "
@@ -309,7 +310,16 @@ def main():
     if args.variant != "bj" or args.form != "plain":
         args.no_flops = args.no_cpu_baseline = True
 
-    run = Runner(system, table, args.form, **headline_kw)
+    run = Runner(system, table, "surrogate" if args.form == "sur" else args.form, **headline_kw)
+    if args.form == "sur":
+        # the surrogate trained on this cell's CN box (99.9th percentile + 0.5)
+        from paper_2310_05279_amd import d3 as d3mod
+        cn = run.calc.coordination().cpu().numpy()
+        cn_hi = float(np.percentile(cn, 99.9) + 0.5)
+        d3mod.d3_c6_surrogate_init(run.calc.ctx, 5)
+        d3mod.d3_c6_surrogate_train(run.calc.ctx, n_samples=1_000_000, epochs=args.sur_epochs,
+                                    lr=1e-2, lr_final=1e-6, seed=4, cn_hi=cn_hi)
+        log("surrogate trained for %d epochs on [0, %.3f]^2" % (args.sur_epochs, cn_hi))
     ms = run.timed(args.steps, args.warmup)
     value = n / (ms * 1e-3)
     ms_graph = run.graphed(args.steps, args.warmup) if args.graph else None
@@ -555,7 +565,8 @@ def main():
     line = {"metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f64" if args.form == "plain" else "f32 (pair arithmetic; f64 sums)",
+            "dtype": {"plain": "f64", "prec": "f32 (pair arithmetic; f64 sums)",
+                      "sur": "bf16 MFMA + f32 (surrogate C6); f64 pair terms"}[args.form],
             "data": "synthetic",
             "config": {"workload": "mof_like_1M (10^6 atoms, H,C,N,O,Zn 4:6:1:2:1, 0.04 "
                                    "atoms/A^3, seed 1000000; synthetic D3 table seed 2310; "
@@ -563,7 +574,9 @@ def main():
                                    "neighbour build in every step)" +
                                    ("" if args.variant == "bj" else
                                     "; variant %s" % args.variant) +
-                                   ("" if args.form == "plain" else "; precision form"),
+                                   {"plain": "", "prec": "; precision form",
+                                    "sur": "; surrogate C6 form (%d training epochs)"
+                                           % args.sur_epochs}[args.form],
                        "n_atoms": n, "parallelism": "single GPU"},
             "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     print(json.dumps(line), flush=True)
