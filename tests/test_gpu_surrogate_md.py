@@ -446,6 +446,42 @@ def test_md_nve_matches_oracle_integrator():
     calc.close()
 
 
+def test_md_precision_form_tracks_oracle_integrator():
+    """The same 20 steps in the precision form against the FP64 oracle's
+    integrator.  A force error of at most 1e-4 eV/A (the precision form's
+    gate) changes the lightest atom's acceleration by at most
+    1e-4 * 9.6485e-3 / 1.008 A/fs^2, so after t = 20 fs velocities may
+    differ by that times t and positions by half that times t^2; the
+    potential energies by the form's 1e-6 eV/atom gate."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    m = synth.mof_like(1000, seed=10)
+    n = m["pos"].shape[0]
+    vel, mass = synth.maxwell_velocities(m["types"], 300.0, seed=300)
+    vel = vel * 20.0
+    calc = d3.D3(TAB, mode="prec", skin=1.0)
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    p = torch.as_tensor(m["pos"], device="cuda").clone()
+    v = torch.as_tensor(vel, device="cuda").clone()
+    ms = torch.as_tensor(mass, device="cuda")
+    steps, dt = 20, 1.0
+    thermo, rebuilds = d3.d3_md_nve(calc.ctx, steps, dt, p, v, ms, every=5)
+    rp, rv, rth = md_oracle.run(m["pos"], vel, mass, m["types"], m["cell"], m["pbc"], TAB,
+                                steps, dt)
+    dp = np.abs(p.cpu().numpy() - rp).max()
+    dv = np.abs(v.cpu().numpy() - rv).max()
+    a_err = 1e-4 * 9.648533212331e-3 / np.min(mass)
+    t = steps * dt
+    de = np.abs(thermo[:, 0] - rth[::5, 0]).max() / n
+    print("precision md: rebuilds=%d max|dx|=%.2e (bound %.1e) max|dv|=%.2e (bound %.1e) "
+          "max|dE_pot|/atom=%.2e" % (rebuilds, dp, 0.5 * a_err * t * t, dv, a_err * t, de),
+          flush=True)
+    assert rebuilds >= 1
+    assert dp <= 0.5 * a_err * t * t and dv <= a_err * t
+    assert de <= 1e-6
+    calc.close()
+
+
 def test_md_list_overflow_restarts_and_matches_oracle():
     """A contracting cell: every atom's velocity points at the centre, so
     the density rises until a device-decided rebuild overflows the lists
