@@ -77,6 +77,43 @@ def test_mof_3000_plain():
     assert gpu["stats"]["max_pot"] > 64 * 4
 
 
+@pytest.mark.parametrize("case", ["mof3000", "graphene144"])
+def test_invariances_relabel_translate_rotate(case):
+    """The GPU path under a relabelling of the atoms, a translation (atoms
+    leave the cell and are wrapped along its periodic axes) and a rotation
+    of cell and positions together (no lattice vector then lies along a
+    coordinate axis): the energy is unchanged, forces and site energies are
+    relabelled or rotated with the atoms, the virial becomes R W R^T.  The
+    inputs differ from the original ones by their own rounding, so the
+    bounds are rounding-sized: 1e-12 relative for E and W, 1e-9 eV/A for
+    forces (every force is also within the oracle gates of the original)."""
+    s = synth.mof_like(3000, seed=31) if case == "mof3000" else synth.bilayer_graphene()
+    n = s["pos"].shape[0]
+    base = run_gpu(s)
+    rng = np.random.default_rng(17)
+    perm = rng.permutation(n)
+    shift = np.array([3.7, -11.2, 25.3])
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    R = q * np.sign(np.linalg.det(q))  # a proper rotation
+    variants = {
+        "relabel": (dict(s, pos=s["pos"][perm], types=s["types"][perm]), perm, np.eye(3)),
+        "translate": (dict(s, pos=s["pos"] + shift), np.arange(n), np.eye(3)),
+        "rotate": (dict(s, pos=s["pos"] @ R.T, cell=s["cell"] @ R.T), np.arange(n), R),
+    }
+    for name, (sv, idx, rot) in variants.items():
+        g = run_gpu(sv)
+        de = abs(g["energy"] - base["energy"])
+        df = np.abs(g["forces"] - base["forces"][idx] @ rot.T).max()
+        du = np.abs(g["atom_energy"] - base["atom_energy"][idx]).max()
+        dw = np.abs(g["virial"].reshape(3, 3) - rot @ base["virial"].reshape(3, 3) @ rot.T).max()
+        wsc = np.abs(base["virial"]).max()
+        print("%s %s: |dE|=%.2e max|dF|=%.2e max|dU_i|=%.2e max|dW|/|W|=%.2e"
+              % (case, name, de, df, du, dw / wsc), flush=True)
+        assert de <= 1e-12 * abs(base["energy"])
+        assert df <= 1e-9 and du <= 1e-12 * np.abs(base["atom_energy"]).max()
+        assert dw <= 1e-12 * wsc
+
+
 def test_tiny_triclinic_cell_many_images():
     """Four atoms in a skewed cell far smaller than R_pot: every atom sees
     hundreds of images of every atom, itself included."""
