@@ -1,7 +1,8 @@
 """The allocation-free entry point (static device scratch, no context)
 against d3_energy_forces_virial on the same inputs, through the C ABI: two
 calls in a row, the second with a smaller input, then a call that exceeds
-the atom limit (refused on the host) and one in the precision form."""
+the atom limit (refused on the host) and one in the precision form; a
+call at the atom limit, and lists too long for the static array."""
 
 import numpy as np
 import pytest
@@ -86,6 +87,32 @@ def test_noalloc_with_zero_damping_and_three_body_term():
                rs6=1.217, rs8=1.0, s9=1.0)
     assert abs(got["energy"][0] - ref["energy"]) / 1500 <= 1e-6
     assert np.abs(got["forces"] - ref["forces"]).max() <= 1e-5
+
+
+def test_noalloc_at_the_atom_limit_and_list_capacity():
+    """Exactly D3_NOALLOC_MAX_ATOMS atoms: bit for bit the context path, and
+    within the oracle's plain gates.  The same atoms with R_pot = 30 A
+    (~4 500 list entries per atom, beyond the ~7 million the static array
+    leaves for lists) are refused with CAPACITY when the lists are sized,
+    before any is written, and the next call on the same array is exact."""
+    from paper_2310_05279_amd import d3
+    n = d3.D3_NOALLOC_MAX_ATOMS
+    s = synth.mof_like(n, seed=5)
+    print("noalloc at the limit: %d atoms" % n, flush=True)
+    want = _context_result(s, "plain")
+    got = _noalloc_result(s, "plain")
+    for k in want:
+        assert np.array_equal(got[k], want[k]), "%s differs" % k
+    ref = R.d3(s["pos"], s["types"], s["cell"], s["pbc"], TAB, cells=True)
+    assert abs(got["energy"][0] - ref["energy"]) / n <= 1e-6
+    assert np.abs(got["forces"] - ref["forces"]).max() <= 1e-5
+    print("noalloc lists beyond the array", flush=True)
+    with pytest.raises(d3.D3Error) as ei:
+        _noalloc_result(s, "plain", r_pot=30.0, r_cn=15.0)
+    assert ei.value.code == d3.D3_ERR_CAPACITY
+    again = _noalloc_result(s, "plain")
+    for k in want:
+        assert np.array_equal(again[k], want[k]), "%s differs after the refusal" % k
 
 
 def test_noalloc_limits_are_refused():
