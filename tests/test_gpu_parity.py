@@ -193,6 +193,67 @@ def test_finite_cluster_no_pbc():
     assert np.abs(gpu["virial"] - sys_["pos"].T @ gpu["forces"]).max() < 1e-10
 
 
+def test_one_context_through_changing_systems():
+    """One context built in turn for systems that differ in size, cell,
+    periodicity and image count, so that every buffer grows and shrinks and
+    the lists, image table and bin layout are re-sized each time: the 144-atom
+    bilayer, a 3 000-atom cube, four atoms in a skewed cell smaller than R_pot
+    (hundreds of images), an empty system, a slab open along z with atoms
+    outside the cell, and a free cluster.  Each against the oracle; then the
+    first system again, bit for bit its first result."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    tiny_cell = np.array([[5.0, 0.0, 0.0], [2.0, 4.6, 0.0], [0.5, 0.7, 5.3]])
+    m600 = synth.mof_like(600, seed=8)
+    slab_pos = m600["pos"].copy()
+    slab_pos[:20, 2] += 0.75 * m600["cell"][2, 2]
+    c80 = synth.cluster(80, 7.0, seed=5)
+    seq = [
+        ("bilayer 144", synth.bilayer_graphene()),
+        ("cube 3000", synth.mof_like(3000, seed=31)),
+        ("tiny skewed", {"pos": np.random.default_rng(2).uniform(0, 1, (4, 3)) @ tiny_cell,
+                         "types": np.array([0, 1, 2, 4], np.int32), "cell": tiny_cell,
+                         "pbc": np.array([1, 1, 1], np.int32)}),
+        ("empty", {"pos": np.zeros((0, 3)), "types": np.zeros(0, np.int32),
+                   "cell": np.eye(3) * 10.0, "pbc": np.array([1, 1, 1], np.int32)}),
+        ("slab 600", {"pos": slab_pos, "types": m600["types"], "cell": m600["cell"],
+                      "pbc": np.array([1, 1, 0], np.int32)}),
+        ("cluster 80", {"pos": c80["pos"] + 7.0, "types": c80["types"],
+                        "cell": np.eye(3) * 14.0, "pbc": np.array([0, 0, 0], np.int32)}),
+    ]
+    calc = d3.D3(TAB)
+
+    def run(sys_):
+        calc.build(sys_["pos"], sys_["types"], sys_["cell"], sys_["pbc"])
+        out = calc.compute()
+        torch.cuda.synchronize()
+        calc.status()
+        res = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+        res["energy"] = float(res["energy"][0])
+        res["cn"] = calc.coordination().cpu().numpy() if sys_["pos"].shape[0] else np.zeros(0)
+        return res
+
+    first = None
+    for label, sys_ in seq:
+        n = sys_["pos"].shape[0]
+        print("one context: %s" % label, flush=True)
+        got = run(sys_)
+        if n == 0:
+            assert got["energy"] == 0.0 and np.all(got["virial"] == 0.0)
+            continue
+        pbc = sys_["pbc"]
+        ref = R.d3(sys_["pos"], sys_["types"], None if not np.any(pbc) else sys_["cell"],
+                   pbc, TAB)
+        compare(got, ref, n, label=label)
+        if first is None:
+            first = got
+    again = run(seq[0][1])
+    for k in ("forces", "virial", "atom_energy", "cn"):
+        assert np.array_equal(again[k], first[k]), k
+    assert again["energy"] == first["energy"]
+    calc.close()
+
+
 def test_single_reference_table():
     """K_e = 1 for every element (C6 constant): the chain term vanishes."""
     tab1 = synth.make_table(force_k=1)
