@@ -122,3 +122,47 @@ def test_package_never_reaches_the_oracle():
             assert not re.search(r"\boracle\b|d3ref", src), f
             if f.endswith(".py"):
                 assert len(re.findall(r"ctypes\.CDLL\(", src)) <= 1, f
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/d3.h compiles as strict C99 (no C++ in the boundary), a C
+    program that takes the address of every declared entry point links
+    against libd3.so, and the calls that need no GPU behave as from Python:
+    the host-only bin planner and the argument checks of d3_create."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    names = _declared()
+    src = ["#include <stdio.h>", '#include "d3.h"', "typedef void (*fn)(void);",
+           "static fn all[] = {" + ", ".join("(fn)%s" % s for s in names) + "};",
+           "int main(void) {",
+           "    double cell[9] = {20.5, 0, 0, 3.0, 19.0, 0, 1.0, 2.0, 18.0};",
+           "    int32_t pbc[3] = {1, 1, 0}, nb[3], reach[3], nrows = -1, ncn = -1;",
+           "    d3_ctx *ctx = NULL;",
+           "    int r = d3_bin_plan(cell, pbc, 13.0, 7.0, 500, nb, reach, &nrows, &ncn, NULL, 0);",
+           "    if (r != D3_OK) return 1;",
+           '    printf("%d %d %d %d %d %d %d %d\\n", nb[0], nb[1], nb[2], reach[0], reach[1],',
+           "           reach[2], nrows, ncn);",
+           "    r = d3_create(NULL, NULL, &ctx);",
+           "    if (r != D3_ERR_INVALID_ARG || ctx != NULL) return 2;",
+           '    printf("%s\\n", d3_last_error());',
+           "    return (int)(sizeof(all) / sizeof(all[0])) == %d ? 0 : 3;" % len(names),
+           "}"]
+    c = tmp_path / "use_d3.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "use_d3"
+    libdir = os.path.dirname(d3.LIB_PATH)
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                    "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe),
+                    "-L" + libdir, "-ld3", "-Wl,-rpath," + libdir], check=True,
+                   capture_output=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    got = [int(v) for v in out.stdout.split("\n")[0].split()]
+    want = d3.d3_bin_plan(np.array([[20.5, 0, 0], [3.0, 19.0, 0], [1.0, 2.0, 18.0]]),
+                          (1, 1, 0), 13.0, 7.0, 500)
+    assert got[:3] == list(want["nb"]) and got[3:6] == list(want["reach"])
+    assert got[6] == len(want["rows"]) and got[7] == want["ncnrows"]
+    assert out.stdout.split("\n")[1].strip()  # the per-thread error message
