@@ -482,6 +482,51 @@ def test_md_precision_form_tracks_oracle_integrator():
     calc.close()
 
 
+def test_md_full_size_lists_stay_valid():
+    """60 NVE steps of the 10^6-atom MOF-like cell at 300 K (1 A skin, lists
+    rebuilt on the device when an atom has moved more than 0.5 A): the lists
+    the run ends with serve the final positions without a rebuild (no stale
+    report), give the result of a fresh build at those positions to rounding,
+    and match the oracle on sampled atoms."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    m = synth.mof_like(1_000_000)
+    vel, mass = synth.maxwell_velocities(m["types"], 300.0, seed=300)
+    calc = d3.D3(TAB, skin=1.0)
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    p = torch.as_tensor(m["pos"], device="cuda").clone()
+    v = torch.as_tensor(vel, device="cuda").clone()
+    ms = torch.as_tensor(mass, device="cuda")
+    _, rebuilds = d3.d3_md_nve(calc.ctx, 60, 1.0, p, v, ms)
+    out = calc.compute(p)  # no rebuild flag: the run's own lists
+    torch.cuda.synchronize()
+    calc.status()  # raises on a stale-list (or any other) report
+    f_md = out["forces"].cpu().numpy()
+    u_md = out["atom_energy"].cpu().numpy()
+    e_md = out["energy"].item()
+    calc.close()
+    pos = p.cpu().numpy()
+    fresh = d3.D3(TAB)
+    fresh.build(pos, m["types"], m["cell"], m["pbc"])
+    ref = fresh.compute()
+    torch.cuda.synchronize()
+    f_new = ref["forces"].cpu().numpy()
+    d_fresh = np.abs(f_md - f_new).max()
+    de_fresh = abs(e_md - ref["energy"].item())
+    fresh.close()
+    L = m["cell"][0, 0]
+    idx = np.random.default_rng(60).choice(pos.shape[0], 8, replace=False)
+    so = O.sampled(np.mod(pos, L), m["types"], m["cell"], m["pbc"], TAB, idx)
+    df = np.abs(f_md[idx] - so["forces"]).max()
+    du = np.abs(u_md[idx] - so["atom_energy"]).max()
+    print("full-size md: %d builds in 60 steps; vs fresh build max|dF|=%.2e |dE|=%.2e; "
+          "vs sampled oracle max|dF|=%.2e max|dU_i|=%.2e" % (rebuilds, d_fresh, de_fresh, df, du),
+          flush=True)
+    assert rebuilds >= 2
+    assert d_fresh <= 1e-12 and de_fresh <= 1e-9 * abs(e_md)
+    assert df <= 1e-5 and du <= 1e-6
+
+
 def test_md_list_overflow_restarts_and_matches_oracle():
     """A contracting cell: every atom's velocity points at the centre, so
     the density rises until a device-decided rebuild overflows the lists
