@@ -254,6 +254,31 @@ def test_one_context_through_changing_systems():
     calc.close()
 
 
+@pytest.mark.parametrize("mode,skin", [("plain", 0.0), ("plain", 1.0), ("prec", 1.0)])
+def test_cutoff_boundaries_are_strict(mode, skin):
+    """Isolated pairs at exactly R_pot = 12 A, one ulp inside it, exactly
+    R_cn = 6 A and one ulp inside it (the first atom of each pair at x = 0, so
+    the displacements are those values exactly in FP64): the
+    strict FP64 tests r^2 < R^2 of the passes leave out the pairs at the
+    cutoffs and keep the ones just inside, as the oracle does, also when the
+    lists (R + skin) hold them and in the precision form."""
+    xs = [12.0, np.nextafter(12.0, 0.0), 6.0, np.nextafter(6.0, 0.0)]
+    pos = []
+    for k, x in enumerate(xs):
+        pos += [[0.0, 5.0 + 30.0 * k, 5.0], [x, 5.0 + 30.0 * k, 5.0]]
+    s_ = {"pos": np.array(pos), "types": np.ones(8, np.int32), "cell": np.diag([30.0, 120.0, 10.0]),
+          "pbc": np.array([0, 0, 0], np.int32)}
+    ref = O.d3(s_["pos"], s_["types"], None, (0, 0, 0), TAB)
+    gpu = run_gpu(s_, mode=mode, skin=skin)
+    print("%s skin %.1f: U=%s CN=%s" % (mode, skin, gpu["atom_energy"], gpu["cn"]), flush=True)
+    assert np.all(gpu["atom_energy"][:2] == 0.0) and np.all(ref["atom_energy"][:2] == 0.0)
+    assert np.all(gpu["atom_energy"][2:] < 0.0) and np.all(ref["atom_energy"][2:] < 0.0)
+    assert np.all(gpu["cn"][:6] == 0.0) and np.all(ref["cn"][:6] == 0.0)
+    assert np.all(gpu["cn"][6:] > 0.0) and np.all(ref["cn"][6:] > 0.0)
+    tol = 1e-6 if mode == "prec" else 1e-13
+    assert abs(gpu["energy"] - ref["energy"]) <= tol * abs(ref["energy"])
+
+
 def test_single_reference_table():
     """K_e = 1 for every element (C6 constant): the chain term vanishes."""
     tab1 = synth.make_table(force_k=1)
