@@ -106,6 +106,30 @@ def test_variants_image_triangles_and_cluster(variant):
         _check(got, ref, s["pos"].shape[0], "plain", "%s %s" % (variant, label))
 
 
+def test_atm_side_at_r_atm_is_left_out():
+    """An isolated 3-4-5 triangle (its longest side exactly 5 A in FP64):
+    with r_atm = 5 A the strict test leaves the triangle out, so the
+    three-body term changes nothing, bit for bit; with r_atm one ulp above
+    5 A it is in, as in the oracle."""
+    s = {"pos": np.array([[0.0, 0.0, 2.0], [3.0, 0.0, 2.0], [0.0, 4.0, 2.0]]),
+         "types": np.array([1, 3, 4], np.int32), "cell": np.eye(3) * 10.0,
+         "pbc": np.array([0, 0, 0])}
+    base = _gpu(s)
+    out = _gpu(s, s9=1.0, r_atm=5.0)
+    for k in ("forces", "atom_energy", "virial"):
+        assert np.array_equal(out[k], base[k]), k
+    assert out["energy"] == base["energy"]
+    r_in = float(np.nextafter(5.0, 6.0))
+    got = _gpu(s, s9=1.0, r_atm=r_in)
+    ref = O.d3(s["pos"], s["types"], None, (0, 0, 0), TAB, O.Params(s9=1.0, r_atm=r_in))
+    ref0 = O.d3(s["pos"], s["types"], None, (0, 0, 0), TAB, O.Params(s9=1.0, r_atm=5.0))
+    print("3-4-5 triangle: E(two-body)=%.12e, E(r_atm=5)=%.12e, E(r_atm=5+ulp)=%.12e (oracle %.12e)"
+          % (base["energy"], out["energy"], got["energy"], ref["energy"]), flush=True)
+    assert ref0["energy"] == pytest.approx(base["energy"], rel=1e-14)
+    assert got["energy"] != base["energy"]
+    _check(got, ref, 3, "plain", "3-4-5 triangle")
+
+
 @pytest.mark.parametrize("variant", sorted(VARIANTS))
 def test_variants_bilayer(variant):
     """The 144-atom bilayer at the workload's cutoffs (12 / 6 A, r_atm 6 A)."""
