@@ -507,6 +507,39 @@ def test_skin_reuse_stale_and_auto_rebuild():
     calc.close()
 
 
+def test_stale_threshold_is_half_the_skin():
+    """The lists stay valid while no atom has moved more than skin/2 from
+    its build position: one atom moved by exactly 0.5 A (skin 1 A; its x in
+    [16, 31.5) A, so x + 0.5 is exact) is not reported stale and the result
+    matches the oracle; one ulp of x further is reported stale."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    m = synth.mof_like(1500, seed=21)
+    k = int(np.nonzero((m["pos"][:, 0] >= 16.0) & (m["pos"][:, 0] < 31.0))[0][0])
+    calc = d3.D3(TAB, skin=1.0)
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    p1 = m["pos"].copy()
+    p1[k, 0] += 0.5
+    assert p1[k, 0] - m["pos"][k, 0] == 0.5
+    out = calc.compute(pos=p1)
+    torch.cuda.synchronize()
+    calc.status()  # not stale
+    ref = R.d3(p1, m["types"], m["cell"], m["pbc"], TAB)
+    g = {key: v.cpu().numpy() for key, v in out.items()}
+    g["energy"] = float(g["energy"][0])
+    g["cn"] = ref["cn"]
+    compare(g, ref, 1500, label="moved by skin/2")
+    p2 = p1.copy()
+    p2[k, 0] = np.nextafter(p1[k, 0], 100.0)
+    assert p2[k, 0] - m["pos"][k, 0] > 0.5
+    calc.compute(pos=p2)
+    torch.cuda.synchronize()
+    with pytest.raises(d3.D3Error) as ei:
+        calc.status()
+    assert ei.value.code == d3.D3_ERR_STALE
+    calc.close()
+
+
 def test_rebuild_flag():
     """D3_REBUILD rebuilds the lists from the given positions before the
     evaluation: after large moves it gives bit for bit what a fresh build
