@@ -527,6 +527,45 @@ def test_md_full_size_lists_stay_valid():
     assert df <= 1e-5 and du <= 1e-6
 
 
+def test_md_surrogate_form_tracks_oracle_integrator(trained):
+    """10 hot steps in the surrogate form against the oracle-driven
+    integrator whose forces come from the FP64 oracle fed the same trained
+    network as its C6 model (exact Eq. 3 outside the trained box).  The
+    surrogate pass matches that oracle to well under 1e-4 eV/A per
+    evaluation; held to that, the lightest atom's acceleration differs by at
+    most 1e-4 * 9.6485e-3 / 1.008 A/fs^2, which after t = 10 fs bounds
+    velocities by that times t and positions by half that times t^2."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    m = synth.mof_like(600, seed=10)
+    vel, mass = synth.maxwell_velocities(m["types"], 300.0, seed=300)
+    vel = vel * 20.0
+    calc = d3.D3(TAB, mode="surrogate", skin=1.0)
+    d3.d3_c6_surrogate_set_weights(calc.ctx, trained["w"])
+    calc.build(m["pos"], m["types"], m["cell"], m["pbc"])
+    p = torch.as_tensor(m["pos"], device="cuda").clone()
+    v = torch.as_tensor(vel, device="cuda").clone()
+    ms = torch.as_tensor(mass, device="cuda")
+    steps, dt = 10, 1.0
+    thermo, rebuilds = d3.d3_md_nve(calc.ctx, steps, dt, p, v, ms, every=5)
+    calc.close()
+    fn = _network_c6(trained["w"], trained["cn_hi"])
+    rp, rv, rth = md_oracle.run(
+        m["pos"], vel, mass, m["types"], m["cell"], m["pbc"], TAB, steps, dt,
+        force_fn=lambda x: O.d3(x, m["types"], m["cell"], m["pbc"], TAB, c6_fn=fn))
+    dp = np.abs(p.cpu().numpy() - rp).max()
+    dv = np.abs(v.cpu().numpy() - rv).max()
+    a_err = 1e-4 * 9.648533212331e-3 / np.min(mass)
+    t = steps * dt
+    de = np.abs(thermo[:, 0] - rth[::5, 0]).max() / m["pos"].shape[0]
+    print("surrogate md: rebuilds=%d max|dx|=%.2e (bound %.1e) max|dv|=%.2e (bound %.1e) "
+          "max|dE_pot|/atom=%.2e" % (rebuilds, dp, 0.5 * a_err * t * t, dv, a_err * t, de),
+          flush=True)
+    assert rebuilds >= 1
+    assert dp <= 0.5 * a_err * t * t and dv <= a_err * t
+    assert de <= 1e-6
+
+
 def test_md_list_overflow_restarts_and_matches_oracle():
     """A contracting cell: every atom's velocity points at the centre, so
     the density rises until a device-decided rebuild overflows the lists
