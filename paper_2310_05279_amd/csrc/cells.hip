@@ -12,8 +12,9 @@
 // Bins are a third of the list cutoff wide (a 7-bin stencil along each
 // axis) or, for long cutoffs, narrow enough to hold a few atoms at the mean
 // density (a deeper stencil).  One wave builds the lists of all atoms of
-// one bin (see k_list); the bins are split between the XCDs in slabs that
-// hold equal shares of the atoms.
+// one bin, or of a unit of two neighbouring bins along the first lattice
+// vector in large periodic cells (see k_list); the bins are split between
+// the XCDs in slabs that hold equal shares of the atoms.
 #include "d3_device.h"
 
 namespace d3 {
@@ -322,9 +323,10 @@ __device__ __forceinline__ int wave_incl_scan(int v)
     return v;
 }
 
-// One wave builds the lists of all atoms of one bin.  The bin's stencil is
-// cut into segments, one per stencil row and periodic image; each segment is
-// one contiguous range of sorted atoms.  TABLE (deep stencils of long
+// One wave builds the lists of all atoms of one unit: a bin, or (UB > 1)
+// UB neighbouring bins of a row, whose stencils then share one candidate
+// set.  The unit's stencil is cut into segments, one per stencil row and
+// periodic image; each segment is one contiguous range of sorted atoms.  TABLE (deep stencils of long
 // cutoffs): the rows come from a host-made table that drops the bins lying
 // wholly beyond the cutoff and puts the rows within R_cn reach first, so
 // the later candidates skip the R_cn test.  Lanes take the segments' candidates
