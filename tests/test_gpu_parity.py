@@ -279,6 +279,37 @@ def test_cutoff_boundaries_are_strict(mode, skin):
     assert abs(gpu["energy"] - ref["energy"]) <= tol * abs(ref["energy"])
 
 
+def test_two_contexts_on_two_streams():
+    """Two contexts, each driven on a stream of its own (default priority),
+    with their builds and evaluations interleaved and no synchronisation
+    between them, then a second round with D3_REBUILD: every result bit for
+    bit what the same system gives alone on the default stream."""
+    torch = _torch()
+    from paper_2310_05279_amd import d3
+    sa = synth.mof_like(3000, seed=31)
+    sb = synth.bilayer_graphene(20, 20, seed=7)
+    want = {"a": run_gpu(sa), "b": run_gpu(sb)}
+    calc = {"a": d3.D3(TAB), "b": d3.D3(TAB)}
+    sys_ = {"a": sa, "b": sb}
+    st = {"a": torch.cuda.Stream(), "b": torch.cuda.Stream()}
+    got = {"a": [], "b": []}
+    for k in ("a", "b"):
+        with torch.cuda.stream(st[k]):
+            calc[k].build(sys_[k]["pos"], sys_[k]["types"], sys_[k]["cell"], sys_[k]["pbc"])
+    for flags in (0, d3.D3_REBUILD):
+        for k in ("a", "b"):
+            with torch.cuda.stream(st[k]):
+                got[k].append(calc[k].compute(flags=flags))
+    torch.cuda.synchronize()
+    for k in ("a", "b"):
+        calc[k].status()
+        for out in got[k]:
+            for key in ("forces", "virial", "atom_energy"):
+                assert np.array_equal(out[key].cpu().numpy(), want[k][key]), (k, key)
+            assert float(out["energy"].cpu()[0]) == want[k]["energy"]
+        calc[k].close()
+
+
 def test_single_reference_table():
     """K_e = 1 for every element (C6 constant): the chain term vanishes."""
     tab1 = synth.make_table(force_k=1)
