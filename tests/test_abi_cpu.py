@@ -166,3 +166,21 @@ def test_header_is_plain_c_and_links(tmp_path):
     assert got[:3] == list(want["nb"]) and got[3:6] == list(want["reach"])
     assert got[6] == len(want["rows"]) and got[7] == want["ncnrows"]
     assert out.stdout.split("\n")[1].strip()  # the per-thread error message
+
+
+def test_readme_c_example_compiles(tmp_path):
+    """The C example in README.md compiles against include/d3.h as strict
+    C99 (it stays in step with the header)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    text = open(os.path.join(ROOT, "README.md")).read()
+    blocks = re.findall(r"```c\n(.*?)```", text, flags=re.S)
+    assert blocks, "README.md has no C example"
+    c = tmp_path / "readme_example.c"
+    c.write_text(blocks[0])
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-c",
+                    "-I", os.path.join(ROOT, "include"), str(c), "-o", str(tmp_path / "ex.o")],
+                   check=True, capture_output=True)
