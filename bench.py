@@ -378,7 +378,7 @@ def main():
             "max_abs_dW": float(np.abs(res_w - ref["virial"]).max()),
             "max_abs_W": float(np.abs(ref["virial"]).max())}
         del ref
-        m1 = 100_000
+        m1 = 250_000
         log("CPU baseline: one thread, passes of %d atoms" % m1)
         _, dt1, _ = cpu_baseline(system, table, n_threads=1, n_eval=m1)
         cpu = {"value": n / dt, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
